@@ -1,0 +1,135 @@
+"""Exact zeroth- and first-order density matrices in FP64 (test infrastructure only).
+
+P0 is the Heaviside step of the Hamiltonian at the chemical potential
+(Sec. II.B, Eq. theta): with H0 = V diag(e) V^T (LAPACK dsyevd, ascending e),
+P0 = V_o V_o^T over the Nocc lowest levels.
+
+P1 is the Gateaux derivative of P along H1 (Sec. IV, definition of D^(1)).  By
+the Daleckii-Krein theorem quoted in Sec. IV, P1 = V (G o V^T H1 V) V^T with G
+the divided differences of the step function: G_ia = G_ai = 1/(e_i - e_a) for i
+occupied and a virtual, zero inside the occupied and the virtual blocks.  This
+is the sum-over-states form
+    P1 = sum_{i occ, a virt} (v_i v_a^T + v_a v_i^T) (v_a^T H1 v_i)/(e_i - e_a).
+
+Pins (tests/test_oracle_exact.py): brute-force finite differences of P(H0 +
+lambda H1) (Eqs. FnD_2/FnD_4) with P computed by a Newton sign iteration that
+never calls eigh; the 2x2 closed form; the diagonal-H0 case; the invariants
+Tr P0 = Nocc, P0^2 = P0, Tr P1 = 0, P0 P1 + P1 P0 = P1 (first-order block of
+D^2 = D, Sec. III.B) and [H0, P1] + [H1, P0] = 0 (first-order block of
+HD = DH).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class DegenerateGap(ValueError):
+    """HOMO-LUMO gap too small: the first-order response is undefined (Sec. III.A
+    restricts the theory to non-degenerate systems)."""
+
+
+def gershgorin(h: np.ndarray):
+    """Gershgorin spectral bounds (eps_1, eps_N) used by the normalisation layer
+    (Sec. II.B; Algorithm 1 inputs)."""
+    d = np.diag(h)
+    r = np.abs(h).sum(axis=1) - np.abs(d)
+    return float(np.min(d - r)), float(np.max(d + r))
+
+
+def eigensystem(h0: np.ndarray):
+    """Ascending eigenvalues and orthonormal eigenvectors (LAPACK dsyevd)."""
+    e, v = np.linalg.eigh(h0)
+    return e, v
+
+
+def check_gap(e: np.ndarray, nocc: int, rel_tol: float = 1e-8) -> float:
+    n = e.shape[0]
+    if not (0 < nocc < n):
+        raise ValueError("need 0 < nocc < N")
+    gap = float(e[nocc] - e[nocc - 1])
+    if gap <= rel_tol * max(1.0, float(e[-1] - e[0])):
+        raise DegenerateGap(f"HOMO-LUMO gap {gap:.3e} too small")
+    return gap
+
+
+def density_matrix(h0: np.ndarray, nocc: int) -> np.ndarray:
+    """P0 = theta(mu I - H0) with Tr P0 = Nocc (Eq. theta)."""
+    e, v = eigensystem(h0)
+    check_gap(e, nocc)
+    vo = v[:, :nocc]
+    return vo @ vo.T
+
+
+def step_divided_differences(e: np.ndarray, nocc: int) -> np.ndarray:
+    """G_ij = theta[e_i, e_j] for the step function, e ascending (Sec. IV)."""
+    n = e.shape[0]
+    g = np.zeros((n, n))
+    ov = 1.0 / (e[:nocc, None] - e[None, nocc:])
+    g[:nocc, nocc:] = ov
+    g[nocc:, :nocc] = ov.T
+    return g
+
+
+def response_from_eigs(e: np.ndarray, v: np.ndarray, h1: np.ndarray, nocc: int) -> np.ndarray:
+    """P1 from eigenpairs sorted ascending: C_ai = (V_v^T H1 V_o)_ai / (e_i - e_a),
+    P1 = V_v C V_o^T + transpose."""
+    vo, vv = v[:, :nocc], v[:, nocc:]
+    y = vv.T @ (h1 @ vo)
+    c = y / (e[None, :nocc] - e[nocc:, None])
+    m = vv @ (c @ vo.T)
+    return m + m.T
+
+
+def density_response(h0: np.ndarray, h1: np.ndarray, nocc: int) -> np.ndarray:
+    """First-order density-matrix response D^(1) along H1."""
+    e, v = eigensystem(h0)
+    check_gap(e, nocc)
+    return response_from_eigs(e, v, h1, nocc)
+
+
+def solve(h0: np.ndarray, h1s, nocc: int):
+    """(P0, [P1_k]) from one eigendecomposition."""
+    e, v = eigensystem(h0)
+    check_gap(e, nocc)
+    vo = v[:, :nocc]
+    return vo @ vo.T, [response_from_eigs(e, v, h, nocc) for h in h1s]
+
+
+def solve_from_factors(e: np.ndarray, q: np.ndarray, h1s, nocc: int):
+    """(P0, [P1_k]) when H0 = Q diag(e) Q^T is given in factored form (the
+    eigenpairs are then known; they are only reordered ascending)."""
+    order = np.argsort(e, kind="stable")
+    es = e[order]
+    check_gap(es, nocc)
+    v = q[:, order]
+    vo = v[:, :nocc]
+    return vo @ vo.T, [response_from_eigs(es, v, h, nocc) for h in h1s]
+
+
+def invariants(h0, h1, p0, p1, nocc: int) -> dict:
+    """Residuals that vanish for the exact P0, P1 (Sec. III.B block identities)."""
+    return {
+        "trace_p0": float(np.trace(p0) - nocc),
+        "idem_p0": float(np.linalg.norm(p0 @ p0 - p0)),
+        "trace_p1": float(np.trace(p1)),
+        "idem_p1": float(np.linalg.norm(p0 @ p1 + p1 @ p0 - p1)),
+        "comm_p0": float(np.linalg.norm(h0 @ p0 - p0 @ h0)),
+        "comm_p1": float(np.linalg.norm(h0 @ p1 - p1 @ h0 + h1 @ p0 - p0 @ h1)),
+    }
+
+
+def fd_response_2pt(pfun, h0, h1, nocc, h):
+    """Central two-point difference (Eq. FnD_2)."""
+    return (pfun(h0 + h * h1, nocc) - pfun(h0 - h * h1, nocc)) / (2.0 * h)
+
+
+def fd_response_4pt(pfun, h0, h1, nocc, h):
+    """Four-point stencil (Eq. FnD_4)."""
+    return (-pfun(h0 + 2 * h * h1, nocc) + 8 * pfun(h0 + h * h1, nocc)
+            - 8 * pfun(h0 - h * h1, nocc) + pfun(h0 - 2 * h * h1, nocc)) / (12.0 * h)
+
+
+def rel_fro(a: np.ndarray, ref: np.ndarray) -> float:
+    """||a - ref||_F / ||ref||_F."""
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(a - ref) / den) if den > 0 else float(np.linalg.norm(a))

@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the DNN-SP2-PT first-order response on one MI355X.
+
+One step = the whole hot path over one synthetic Hamiltonian: Gershgorin bounds
+and normalisation of H0, the first-order input layer, every deep layer
+(split-precision MFMA products, FP64 traces and sigma, fused update/split/norm
+kernels, stopping tests) until each D1 test fires, and the FP64 outputs P0, P1.
+Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--precision P]
+                  [--no-fp64] [--no-cpu] [--no-oracle]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"split_fp16": 2500.0, "split_bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+METRIC = "DMPT TFLOP/s + time-to-P1 at rel Frobenius err≤1e-3 vs plain FP64 GPU"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from workloads import config1, config2, config3
+    if name == "c3":
+        return config3()
+    if name == "c2":
+        return config2()
+    if name == "c1":
+        return config1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_flops(n, k_active_per_layer, x_layers, precision):
+    """FLOPs the method must issue (2 per FMA), summed over the layers.
+
+    Per layer the network forms X = S^2 (symmetric: N^3/2 FMA for the upper
+    triangle) while D0 is active and X1_k = S S1_k + S1_k S (symmetric: N^3
+    FMA) for every active response.  The split forms issue three half-precision
+    products per matrix product (hi*hi, hi*lo, lo*hi)."""
+    mult = 3.0 if precision.startswith("split") else 1.0
+    tot = 0.0
+    for layer, ka in enumerate(k_active_per_layer, start=1):
+        fma = (0.5 * n ** 3 if layer <= x_layers else 0.0) + ka * n ** 3
+        tot += 2.0 * mult * fma
+    return tot
+
+
+def k_active(stats):
+    L = stats["layers"]
+    ends = [d if d > 0 else L for d in stats["d1_layer"]]
+    return [sum(1 for e in ends if layer <= e) for layer in range(1, L + 1)]
+
+
+def oracle_errors(p, P0, P1s):
+    from oracle import exact
+    t = time.perf_counter()
+    if p.basis.kind == "brickwall":
+        r0, r1s = exact.solve_from_brickwall(p.basis.e, p.basis.layers, p.basis.layer_offsets(),
+                                             p.basis.block, p.H1, p.nocc)
+    else:
+        r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+    log(f"oracle reference: {time.perf_counter() - t:.1f} s")
+    return exact.rel_fro(P0, r0), [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)]
+
+
+def cpu_baseline(p, workload, layers):
+    """The FP64 oracle (eigh + sum-over-states) on the host cores, on a bounded
+    sample: the same recipe at N_s = min(N, 4096), time scaled by (N/N_s)^3."""
+    from oracle import exact
+    from workloads import banded_gapped_problem, dense_gapped_problem
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    ns = min(p.N, 4096)
+    if ns == p.N:
+        q = p
+    elif p.basis.kind == "brickwall":
+        q = banded_gapped_problem(ns, ns // 2, p.gap, p.seed, block=p.basis.block, k=p.k)
+    else:
+        q = dense_gapped_problem(ns, ns // 2, p.gap, p.seed, k=p.k)
+    t = time.perf_counter()
+    exact.solve(q.H0, q.H1, q.nocc)
+    dt = time.perf_counter() - t
+    scale = (p.N / ns) ** 3
+    t_full = dt * scale
+    value = 5.0 * p.N ** 3 * layers / t_full / 1e12
+    return {"value": value, "unit": "TFLOP/s (paper convention, FMA = 1)", "cores": cores,
+            "kind": "oracle",
+            "sample": f"exact FP64 oracle (LAPACK eigh + sum-over-states) on the N={ns} instance "
+                      f"of the {workload} recipe: {dt:.2f} s, scaled by (N/{ns})^3 = {scale:.0f} "
+                      f"to {t_full:.0f} s for N={p.N}",
+            "seconds_full_estimate": t_full}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1"])
+    ap.add_argument("--precision", default="split_fp16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the error vs the oracle")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2203_09621_amd as dm
+
+    t = time.perf_counter()
+    p = make_workload(args.workload)
+    log(f"workload {p.name}: N={p.N} nocc={p.nocc} k={p.k}  ({time.perf_counter() - t:.1f} s)")
+    dev = torch.device("cuda:0")
+    H0 = torch.from_numpy(p.H0).to(dev)
+    H1s = [torch.from_numpy(h).to(dev) for h in p.H1]
+    P0 = torch.empty_like(H0)
+    P1s = [torch.empty_like(H0) for _ in H1s]
+
+    ctx = dm.dmpt_init(H0, p.nocc, k_max=p.k, precision=args.precision, timing=True)
+
+    def step():
+        dm.dmpt_set_hamiltonian(ctx, H0)
+        return dm.dmpt_response(ctx, H1s, P0, P1s)[2]
+
+    for w in range(args.warmup):
+        st = step()
+        log(f"warmup {w}: {st['ms']:.1f} ms, layers {st['layers']}, d0 {st['d0_layer']}, "
+            f"d1 {st['d1_layer']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    st = stats[-1]
+    layers = st["layers"]
+    log(f"timed {args.steps} steps: {ms:.2f} ms/step, layers {layers}")
+
+    # paper convention (Eq. flop rate formula): 5 N^3 per layer, FMA counted once
+    value = 5.0 * p.N ** 3 * layers / (ms * 1e-3) / 1e12
+    alg = algorithmic_flops(p.N, k_active(st), st["x_layers"], args.precision)
+    prod_ms = sum(s["product_ms"] for s in stats)
+    launches = sum(s["product_launches"] for s in stats)
+    achieved = alg * args.steps / (prod_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    out = {
+        "metric": METRIC, "value": round(value, 3),
+        "unit": "TFLOP/s (paper convention: 5 N^3 per layer, FMA = 1)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"split_fp16": "f16", "split_bf16": "bf16", "fp32": "f32", "fp64": "f64"}[
+            args.precision],
+        "data": "synthetic",
+        "config": {"workload": p.name, "N": p.N, "nocc": p.nocc, "k": p.k,
+                   "precision": args.precision, "accumulate": "f64" if args.precision == "fp64"
+                   else "f32", "layers": layers, "d0_layer": st["d0_layer"],
+                   "d1_layer": st["d1_layer"]},
+        "time_to_p1_ms": round(ms, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "k_products_split" if args.precision.startswith("split")
+                     else "k_products_direct",
+                     "avg_launch_ms": round(prod_ms / max(launches, 1), 4),
+                     "launches": launches},
+    }
+    if not args.no_oracle:
+        e0, e1 = oracle_errors(p, P0.cpu().numpy(), [q.cpu().numpy() for q in P1s])
+        out["rel_fro_err"] = {"P0": e0, "P1": e1}
+        log(f"errors vs oracle: P0 {e0:.2e}  P1 {[f'{x:.2e}' for x in e1]}")
+    if not args.no_fp64 and args.precision != "fp64":
+        dm.dmpt_destroy(ctx)
+        ctx = None
+        c64 = dm.dmpt_init(H0, p.nocc, k_max=p.k, precision="fp64", timing=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        dm.dmpt_set_hamiltonian(c64, H0)
+        s64 = dm.dmpt_response(c64, H1s, P0, P1s)[2]
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - ta) * 1e3
+        alg64 = algorithmic_flops(p.N, k_active(s64), s64["x_layers"], "fp64")
+        out["fp64_gpu"] = {"ms": round(ms64, 2), "layers": s64["layers"],
+                           "speedup_of_split": round(ms64 / ms, 2),
+                           "mfma_tflops": round(alg64 / (s64["product_ms"] * 1e-3) / 1e12, 2),
+                           "peak": PEAK_TFLOPS["fp64"]}
+        log(f"fp64 GPU form: {ms64:.1f} ms, layers {s64['layers']}, speedup {ms64 / ms:.2f}x")
+        dm.dmpt_destroy(c64)
+    if ctx is not None:
+        dm.dmpt_destroy(ctx)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, args.workload, layers)
+        log(f"cpu baseline: {out['cpu_baseline']['sample']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/*
+ * dmpt.h -- C ABI of the MI355X (gfx950) DNN-SP2-PT library: the zeroth-order
+ * density matrix P0 and its first-order responses P1_k of a symmetric
+ * Hamiltonian, computed as a deep layered network of SP2 steps.
+ *
+ * Method (arXiv:2203.09621):
+ *   normalisation layer (Sec. III.A, Algorithm 1)
+ *       S0 = (eps_N I - H0)/(eps_N - eps_1),  S1_k = -H1_k/(eps_N - eps_1),
+ *       eps_1, eps_N Gershgorin bounds of H0 (Sec. II.B);
+ *   deep layer n (Eqs. S_n detailed and dB, first order)
+ *       X = S^2,  X1_k = S S1_k + S1_k S,
+ *       S <- sigma X + (1 - sigma) S,  S1_k <- sigma X1_k + (1 - sigma) S1_k,
+ *       sigma = +-1 from an FP64 trace test against Nocc (Algorithm 1);
+ *   stopping: the D0 test of Algorithm 2 and the parameter-free D1 test of
+ *       Eq. (ConvCrit) / Algorithm 3 with C_pt = 9.
+ *   The limits are P0 = theta(mu I - H0) (Eq. theta) and P1_k, the Gateaux
+ *   derivative of P along H1_k (Sec. IV).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are dense, symmetric, N x N, FP64, row-major with leading
+ *     dimension N (symmetry makes row/column major identical).  All matrix
+ *     pointers are DEVICE pointers owned by the caller.  Arrays of matrix
+ *     pointers (H1, P1) are HOST arrays of device pointers.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     is enqueued on it; the call returns after the results are written and
+ *     the statistics are readable (one synchronisation at the end).
+ *   - No exception crosses the ABI.  A non-OK status leaves the outputs
+ *     undefined; dmpt_last_error() gives a human-readable reason.
+ *   - One context per stream; contexts are not thread-safe.
+ *   - The library owns its workspace (allocated in dmpt_init, released by
+ *     dmpt_destroy); H0 may be freed after dmpt_init returns.
+ */
+#ifndef DMPT_H
+#define DMPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DMPT_OK = 0,
+  DMPT_EINVAL = -1,      /* bad argument: sizes, Nocc not in (0, N), k out of range, NULL */
+  DMPT_ENOMEM = -2,      /* device allocation failed */
+  DMPT_EHIP = -3,        /* a HIP runtime call failed */
+  DMPT_ENOCONV = -4,     /* layer cap reached before every response met its D1 test */
+  DMPT_ENONFINITE = -5,  /* a trace or norm became NaN/Inf, or a split operand overflowed */
+  DMPT_EASYM = -6,       /* symmetry check enabled and H0 or an H1 is not exactly symmetric */
+  DMPT_ENOTSUP = -7      /* precision mode not built / not supported on this device */
+} dmpt_status;
+
+/* Arithmetic of the layer products.  Traces, sigma, stopping tests, the
+ * Gershgorin bounds and the outputs are FP64 in every mode. */
+typedef enum {
+  DMPT_FP64 = 0,        /* FP64 MFMA products, FP64 layer state (the plain FP64 GPU form) */
+  DMPT_FP32 = 1,        /* FP32 MFMA products, FP32 layer state */
+  DMPT_SPLIT_BF16 = 2,  /* X ~ hi*hi + hi*lo + lo*hi with BF16 hi/lo parts, FP32 accumulate */
+  DMPT_SPLIT_FP16 = 3   /* same with FP16 hi/lo parts; lo and S1 carry power-of-two scales */
+} dmpt_precision;
+
+#define DMPT_MAX_K 8          /* most perturbations per context */
+#define DMPT_MAX_LAYERS 256   /* hard cap on the layer count */
+
+typedef struct {
+  int32_t precision;       /* dmpt_precision; default DMPT_SPLIT_FP16 */
+  int32_t max_layers;      /* default 100, at most DMPT_MAX_LAYERS */
+  int32_t check_symmetry;  /* nonzero: dmpt_init / dmpt_response verify exact symmetry (EASYM) */
+  int32_t poll_every;      /* host checks the device stop flag every this many layers (0 = auto) */
+  int32_t timing;          /* nonzero: time every layer-product launch with hipEvents on the
+                              context's stream (dmpt_stats.product_ms / product_launches) */
+} dmpt_options;
+
+typedef struct {
+  int32_t layers;                  /* layers run (index of the last layer) */
+  int32_t d0_layer;                /* layer at which the D0 test fired (0 = never) */
+  int32_t d1_layer[DMPT_MAX_K];    /* layer at which each D1 test fired (0 = never) */
+  int32_t k;                       /* number of responses */
+  int32_t converged;               /* 1 if every D1 test fired */
+  int8_t sigma[DMPT_MAX_LAYERS];   /* sigma_n of layers 1..layers (+1: x^2, -1: 2x - x^2) */
+  double eps1, epsN;               /* Gershgorin bounds of H0 */
+  double n_s;                      /* tracked occupation N_S of the returned S0 */
+  double idem0;                    /* ||P0 - P0^2||_F at the D0 layer (layer arithmetic) */
+  double idem1[DMPT_MAX_K];        /* ||P1 - (P0 P1 + P1 P0)||_F at the D1 layer (layer arithmetic) */
+  double trace_p0;                 /* Tr P0 (FP64 over the returned matrix) */
+  double trace_p1[DMPT_MAX_K];     /* Tr P1_k (FP64 over the returned matrix) */
+  double ms;                       /* device time of dmpt_response (hipEvents) */
+  double product_ms;               /* summed duration of the layer-product launches (timing on) */
+  int32_t product_launches;        /* layer-product launches timed */
+  int32_t x_layers;                /* layers that formed X = S^2 (1..d0_layer) */
+} dmpt_stats;
+
+typedef struct dmpt_ctx dmpt_ctx;
+
+/* Fill `opt` with the defaults. */
+void dmpt_default_options(dmpt_options* opt);
+
+/* Set up a context for H0 (device, N x N FP64, symmetric) with Nocc occupied
+ * states.  Computes the Gershgorin bounds and the normalised S0 (Algorithm 1
+ * initial transform) into library-owned workspace sized for up to k_max
+ * responses.  Errors: EINVAL (N < 1, Nocc not in (0, N), k_max not in
+ * [1, DMPT_MAX_K], NULL), ENOMEM, EHIP, ENOTSUP, EASYM, ENONFINITE. */
+dmpt_status dmpt_init(dmpt_ctx** ctx, const double* H0, int64_t N, int64_t Nocc, int32_t k_max,
+                      const dmpt_options* opt /* NULL = defaults */, void* stream);
+
+/* Replace the Hamiltonian of a context (same N, Nocc, precision): recompute
+ * the Gershgorin bounds and the normalised S0 into the existing workspace.
+ * Allocates nothing.  Errors: EINVAL, EHIP, EASYM, ENONFINITE. */
+dmpt_status dmpt_set_hamiltonian(dmpt_ctx* ctx, const double* H0);
+
+/* Run Algorithms 1-3 for k perturbations H1[0..k-1] (host array of device
+ * pointers).  Writes P0 (device N x N FP64, may be NULL) and P1[j] (host
+ * array of k device pointers, N x N FP64).  The S0 chain is shared; each
+ * response has its own D1 test and is frozen once it passes.  Returns
+ * ENOCONV when the layer cap is reached first (outputs then hold the last
+ * layer).  `st` may be NULL. */
+dmpt_status dmpt_response(dmpt_ctx* ctx, const double* const* H1, int32_t k, double* P0,
+                          double* const* P1, dmpt_stats* st);
+
+/* Release the context and its workspace.  NULL is allowed. */
+void dmpt_destroy(dmpt_ctx* ctx);
+
+/* Short name of a status code (static storage). */
+const char* dmpt_status_str(dmpt_status s);
+
+/* Reason for the most recent non-OK status on the calling thread. */
+const char* dmpt_last_error(void);
+
+/* ---- kernel-level entry points (for parity tests of the layer products) ----
+ * One activation of a deep layer without any decision: for symmetric S and S1
+ * (device, N x N FP64) computes X = S^2 and X1 = S S1 + S1 S (device, N x N
+ * FP64 out; X1 may be NULL when S1 is NULL) with the same split, tiling and
+ * MFMA code the layers use (Eqs. S0 tensor core and S0S1 tensor core, in the
+ * chosen precision).  The S1 split scale is chosen from max|S1| as in a
+ * layer.  Errors: EINVAL, ENOMEM, EHIP, ENOTSUP. */
+dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, const double* S1,
+                                double* X, double* X1, void* stream);
+
+/* Gershgorin bounds (Sec. II.B) of a device N x N FP64 matrix into host eps[2]. */
+dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps /* host, 2 */, void* stream);
+
+/* Device check of the MFMA lane layouts the kernels assume (f16 32x32x16,
+ * bf16 32x32x16, f32 16x16x4, f64 16x16x4).  Returns DMPT_OK when every
+ * layout matches; `detail` (host, may be NULL) receives a bitmask of
+ * mismatching instructions. */
+dmpt_status dmpt_selftest_mfma(int32_t* detail, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMPT_H */

@@ -106,6 +106,56 @@ def solve_from_factors(e: np.ndarray, q: np.ndarray, h1s, nocc: int):
     return vo @ vo.T, [response_from_eigs(es, v, h, nocc) for h in h1s]
 
 
+def _apply_layers(m, layers, offsets, block, transpose: bool):
+    """In place: M <- Q M (Q = L_last ... L_0) or M <- Q^T M, for block-diagonal
+    orthogonal layers L_l = blockdiag(I_offset_l, blocks..., I_rest)."""
+    seq = list(zip(layers, offsets))
+    # Q M = L1 (L0 M): L0 first.  Q^T M = L0^T (L1^T M): L1^T first.
+    for blocks, off in (seq[::-1] if transpose else seq):
+        for r in range(blocks.shape[0]):
+            rows = slice(off + r * block, off + (r + 1) * block)
+            o = blocks[r].T if transpose else blocks[r]
+            m[rows] = o @ m[rows]
+
+
+def _congruence(m, layers, offsets, block, transpose: bool):
+    """Q M Q^T (transpose=False) or Q^T M Q (transpose=True) for symmetric M."""
+    a = np.array(m, copy=True)
+    _apply_layers(a, layers, offsets, block, transpose)
+    a = np.ascontiguousarray(a.T)
+    _apply_layers(a, layers, offsets, block, transpose)
+    a += a.T
+    a *= 0.5
+    return a
+
+
+def solve_from_brickwall(e: np.ndarray, layers, offsets, block: int, h1s, nocc: int):
+    """(P0, [P1_k]) for H0 = Q diag(e) Q^T with Q a product of block-diagonal
+    orthogonal layers (the factors as drawn).  The same Daleckii-Krein formula
+    as ``response_from_eigs``; Q and Q^T are applied layer by layer, so the
+    cost is O(N^2 b) per application instead of O(N^3)."""
+    n = e.shape[0]
+    order = np.argsort(e, kind="stable")
+    check_gap(e[order], nocc)
+    occ = np.zeros(n, dtype=bool)
+    occ[order[:nocc]] = True
+    p0 = _congruence(np.diag(occ.astype(float)), layers, offsets, block, transpose=False)
+    p1s = []
+    rows = 2048
+    for h1 in h1s:
+        y = _congruence(h1, layers, offsets, block, transpose=True)   # V^T H1 V
+        for i0 in range(0, n, rows):
+            i1 = min(n, i0 + rows)
+            # G_ia = G_ai = 1/(e_i - e_a), i occupied, a virtual (symmetric)
+            d = e[i0:i1, None] - e[None, :]
+            inv = 1.0 / np.where(d == 0, 1.0, d)
+            g = np.where(occ[i0:i1, None] & ~occ[None, :], inv, 0.0)
+            g -= np.where(~occ[i0:i1, None] & occ[None, :], inv, 0.0)
+            y[i0:i1] *= g
+        p1s.append(_congruence(y, layers, offsets, block, transpose=False))
+    return p0, p1s
+
+
 def invariants(h0, h1, p0, p1, nocc: int) -> dict:
     """Residuals that vanish for the exact P0, P1 (Sec. III.B block identities)."""
     return {

@@ -1,0 +1,19 @@
+"""MI355X (gfx950) DNN-SP2-PT: zeroth- and first-order density matrices by a deep
+layered network of SP2 steps, with hand-written HIP kernels behind a C ABI
+(include/dmpt.h).  Python only marshals arguments; the HIP library does the work
+and must be built (``python -m paper_2203_09621_amd.build``).  The library is
+loaded on first use of any entry point; a missing library raises ImportError."""
+
+_API = ("EXPORTS", "PRECISION", "DmptError", "dmpt_destroy", "dmpt_gershgorin", "dmpt_init",
+        "dmpt_layer_products", "dmpt_response", "dmpt_selftest_mfma", "dmpt_set_hamiltonian",
+        "solve")
+
+
+def __getattr__(name):
+    if name in _API:
+        from . import _native
+        return getattr(_native, name)
+    raise AttributeError(name)
+
+
+__all__ = list(_API)

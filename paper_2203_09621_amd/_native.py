@@ -1,0 +1,212 @@
+"""ctypes binding of libdmpt (the C ABI in include/dmpt.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+If the shared library is missing the import of this module fails loudly;
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int8, c_int32, c_int64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmpt.so")
+
+DMPT_MAX_K = 8
+DMPT_MAX_LAYERS = 256
+
+STATUS = {0: "DMPT_OK", -1: "DMPT_EINVAL", -2: "DMPT_ENOMEM", -3: "DMPT_EHIP",
+          -4: "DMPT_ENOCONV", -5: "DMPT_ENONFINITE", -6: "DMPT_EASYM", -7: "DMPT_ENOTSUP"}
+PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
+
+# every entry point declared in include/dmpt.h
+EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
+           "dmpt_destroy",
+           "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
+           "dmpt_selftest_mfma"]
+
+
+class DmptOptions(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("max_layers", c_int32),
+                ("check_symmetry", c_int32), ("poll_every", c_int32), ("timing", c_int32)]
+
+
+class DmptStats(ctypes.Structure):
+    _fields_ = [("layers", c_int32), ("d0_layer", c_int32),
+                ("d1_layer", c_int32 * DMPT_MAX_K), ("k", c_int32), ("converged", c_int32),
+                ("sigma", c_int8 * DMPT_MAX_LAYERS),
+                ("eps1", c_double), ("epsN", c_double), ("n_s", c_double), ("idem0", c_double),
+                ("idem1", c_double * DMPT_MAX_K), ("trace_p0", c_double),
+                ("trace_p1", c_double * DMPT_MAX_K), ("ms", c_double),
+                ("product_ms", c_double), ("product_launches", c_int32), ("x_layers", c_int32)]
+
+    def as_dict(self) -> dict:
+        k = self.k
+        return {
+            "layers": self.layers, "d0_layer": self.d0_layer,
+            "d1_layer": list(self.d1_layer[:k]), "k": k, "converged": bool(self.converged),
+            "sigma": list(self.sigma[:self.layers]), "eps1": self.eps1, "epsN": self.epsN,
+            "n_s": self.n_s, "idem0": self.idem0, "idem1": list(self.idem1[:k]),
+            "trace_p0": self.trace_p0, "trace_p1": list(self.trace_p1[:k]), "ms": self.ms,
+            "product_ms": self.product_ms, "product_launches": self.product_launches,
+            "x_layers": self.x_layers,
+        }
+
+
+class DmptError(RuntimeError):
+    def __init__(self, status: int, message: str, stats: dict | None = None):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.stats = stats
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2203_09621_amd.build` (no fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.dmpt_default_options.argtypes = [POINTER(DmptOptions)]
+    lib.dmpt_default_options.restype = None
+    lib.dmpt_init.argtypes = [POINTER(c_void_p), c_void_p, c_int64, c_int64, c_int32,
+                              POINTER(DmptOptions), c_void_p]
+    lib.dmpt_init.restype = c_int32
+    lib.dmpt_set_hamiltonian.argtypes = [c_void_p, c_void_p]
+    lib.dmpt_set_hamiltonian.restype = c_int32
+    lib.dmpt_response.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
+                                  POINTER(c_void_p), POINTER(DmptStats)]
+    lib.dmpt_response.restype = c_int32
+    lib.dmpt_destroy.argtypes = [c_void_p]
+    lib.dmpt_destroy.restype = None
+    lib.dmpt_status_str.argtypes = [c_int32]
+    lib.dmpt_status_str.restype = c_char_p
+    lib.dmpt_last_error.argtypes = []
+    lib.dmpt_last_error.restype = c_char_p
+    lib.dmpt_layer_products.argtypes = [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]
+    lib.dmpt_layer_products.restype = c_int32
+    lib.dmpt_gershgorin.argtypes = [c_void_p, c_int64, POINTER(c_double), c_void_p]
+    lib.dmpt_gershgorin.restype = c_int32
+    lib.dmpt_selftest_mfma.argtypes = [POINTER(c_int32), c_void_p]
+    lib.dmpt_selftest_mfma.restype = c_int32
+    return lib
+
+
+LIB = _load()
+
+
+def last_error() -> str:
+    return LIB.dmpt_last_error().decode()
+
+
+def _check(status: int, stats: dict | None = None):
+    if status != 0:
+        raise DmptError(status, last_error(), stats)
+
+
+# ---------------------------------------------------------------- torch marshalling
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise TypeError(f"{name} must be a contiguous square float64 tensor")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def default_options() -> DmptOptions:
+    o = DmptOptions()
+    LIB.dmpt_default_options(byref(o))
+    return o
+
+
+# ---------------------------------------------------------------- entry points
+def dmpt_init(H0, nocc: int, k_max: int = 1, precision: str = "split_fp16",
+              max_layers: int = 100, check_symmetry: bool = False, poll_every: int = 0,
+              timing: bool = False, stream=None) -> c_void_p:
+    """dmpt_init: Gershgorin bounds and the normalised S0 of H0 (device FP64)."""
+    o = default_options()
+    o.precision = PRECISION[precision]
+    o.max_layers = max_layers
+    o.check_symmetry = int(check_symmetry)
+    o.poll_every = poll_every
+    o.timing = int(timing)
+    ctx = c_void_p()
+    _check(LIB.dmpt_init(byref(ctx), _dev(H0, "H0"), H0.shape[0], int(nocc), int(k_max),
+                         byref(o), _stream(stream)))
+    return ctx
+
+
+def dmpt_set_hamiltonian(ctx: c_void_p, H0) -> None:
+    """dmpt_set_hamiltonian: new H0 of the same size; no allocation."""
+    _check(LIB.dmpt_set_hamiltonian(ctx, _dev(H0, "H0")))
+
+
+def dmpt_response(ctx: c_void_p, H1s, P0=None, P1s=None):
+    """dmpt_response: P0 and P1_k for the perturbations H1s (device FP64).
+    Returns (P0, [P1_k], stats)."""
+    torch = _torch()
+    k = len(H1s)
+    n = H1s[0].shape[0]
+    if P1s is None:
+        P1s = [torch.empty_like(h) for h in H1s]
+    if P0 is None:
+        P0 = torch.empty_like(H1s[0])
+    h_arr = (c_void_p * k)(*[_dev(h, "H1").value for h in H1s])
+    p_arr = (c_void_p * k)(*[_dev(p, "P1").value for p in P1s])
+    st = DmptStats()
+    status = LIB.dmpt_response(ctx, h_arr, k, _dev(P0, "P0"), p_arr, byref(st))
+    stats = st.as_dict()
+    _check(status, stats)
+    del n
+    return P0, P1s, stats
+
+
+def dmpt_destroy(ctx: c_void_p) -> None:
+    LIB.dmpt_destroy(ctx)
+
+
+def dmpt_layer_products(S, S1=None, precision: str = "split_fp16", stream=None):
+    """dmpt_layer_products: X = S^2 and X1 = S S1 + S1 S with the layer kernels."""
+    torch = _torch()
+    X = torch.empty_like(S)
+    X1 = torch.empty_like(S) if S1 is not None else None
+    _check(LIB.dmpt_layer_products(PRECISION[precision], S.shape[0], _dev(S, "S"),
+                                   _dev(S1, "S1") if S1 is not None else None,
+                                   _dev(X, "X"), _dev(X1, "X1") if X1 is not None else None,
+                                   _stream(stream)))
+    return X, X1
+
+
+def dmpt_gershgorin(H, stream=None):
+    eps = (c_double * 2)()
+    _check(LIB.dmpt_gershgorin(_dev(H, "H"), H.shape[0], eps, _stream(stream)))
+    return float(eps[0]), float(eps[1])
+
+
+def dmpt_selftest_mfma(stream=None) -> int:
+    detail = c_int32(0)
+    status = LIB.dmpt_selftest_mfma(byref(detail), _stream(stream))
+    if status not in (0, -7):
+        _check(status)
+    return detail.value
+
+
+def solve(H0, H1s, nocc: int, precision: str = "split_fp16", max_layers: int = 100, **kw):
+    """One-shot dmpt_init + dmpt_response + dmpt_destroy."""
+    ctx = dmpt_init(H0, nocc, k_max=len(H1s), precision=precision, max_layers=max_layers, **kw)
+    try:
+        return dmpt_response(ctx, H1s)
+    finally:
+        dmpt_destroy(ctx)

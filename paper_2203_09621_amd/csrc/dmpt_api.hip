@@ -1,0 +1,529 @@
+// C ABI and host driver of the DNN-SP2-PT layer loop (Algorithm 1).
+//
+// The host only enqueues kernels: every decision of Algorithms 1-3 is taken
+// by single-workgroup kernels on the device and stored in a LayerState, which
+// the layer kernels read.  The host looks at the device stop flag every
+// `poll_every` layers; kernels of layers enqueued after the stop return at once.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dmpt_internal.h"
+
+using namespace dmpt;
+
+namespace {
+
+thread_local std::string g_err;
+
+dmpt_status fail(dmpt_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return fail(DMPT_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));       \
+  } while (0)
+
+bool is_split(dmpt_precision p) { return p == DMPT_SPLIT_FP16 || p == DMPT_SPLIT_BF16; }
+size_t elem_bytes(dmpt_precision p) { return p == DMPT_FP64 ? 8 : 4; }
+int lo_shift(dmpt_precision p) {
+  return p == DMPT_SPLIT_FP16 ? kLoShiftF16 : (p == DMPT_SPLIT_BF16 ? kLoShiftBF16 : 0);
+}
+
+// Upper-triangle tiles of each output, grouped 8 tile-rows at a time and
+// walked column by column, so that consecutive items share row panels.
+// Responses first (two products per tile), then X = S^2.
+std::vector<TileItem> build_items(int T, int k) {
+  std::vector<TileItem> v;
+  const int GR = 8;
+  auto add_out = [&](int out) {
+    for (int g0 = 0; g0 < T; g0 += GR) {
+      const int g1 = std::min(T, g0 + GR);
+      for (int tj = g0; tj < T; ++tj)
+        for (int ti = g0; ti < std::min(g1, tj + 1); ++ti) {
+          TileItem it;
+          it.out = (int16_t)out;
+          it.pad = 0;
+          it.ti = ti;
+          it.tj = tj;
+          v.push_back(it);
+        }
+    }
+  };
+  for (int j = 0; j < k; ++j) add_out(1 + j);
+  add_out(0);
+  return v;
+}
+
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  hipError_t get(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct dmpt_ctx {
+  dmpt_precision prec;
+  int64_t n, nocc, np;
+  int k_max, max_layers, poll, check_sym;
+  hipStream_t stream;
+  LayerState* st;
+  void* s_init;
+  void* s_master;
+  void* s_hi;
+  void* s_lo;
+  void* x;
+  void* s1buf[kMaxK][2];
+  void* s1_hi[kMaxK];
+  void* s1_lo[kMaxK];
+  double* part;       // reduction partials
+  double* dscal;      // device scalars (traces)
+  int32_t* dflag;
+  TileItem* items[kMaxK + 1];
+  int n_items[kMaxK + 1];
+  LayerState* hstate; // pinned host copy
+  int32_t* hflag;     // pinned host flag
+  double* hscal;      // pinned host scalars
+  hipEvent_t ev0, ev1;
+  int timing;
+  hipEvent_t pev[2 * kMaxLayers];  // per-layer product launch bracket (timing on)
+  DevAlloc mem;
+};
+
+namespace {
+
+constexpr size_t kPartFro0 = 0;
+constexpr size_t kPartFro1 = kRedBlocks;
+constexpr size_t kPartMax1 = kPartFro1 + (size_t)kMaxK * kRedBlocks;
+constexpr size_t kPartGersh = kPartMax1 + (size_t)kMaxK * kRedBlocks;
+constexpr size_t kPartMaxabs = kPartGersh + 3 * 512;
+constexpr size_t kPartTotal = kPartMaxabs + kRedBlocks;
+
+void ctx_free(dmpt_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  c->mem.release();
+  if (c->hstate) hipHostFree(c->hstate);
+  if (c->hflag) hipHostFree(c->hflag);
+  if (c->hscal) hipHostFree(c->hscal);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  for (int i = 0; i < 2 * kMaxLayers; ++i)
+    if (c->pev[i]) hipEventDestroy(c->pev[i]);
+  delete c;
+}
+
+dmpt_status check_symmetric(const double* H, int64_t n, int32_t* dflag, int32_t* hflag,
+                            hipStream_t s, const char* what) {
+  HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int32_t), s));
+  HIPCHK(launch_symcheck(H, n, dflag, s));
+  HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (*hflag == 1) return fail(DMPT_EASYM, std::string(what) + " is not exactly symmetric");
+  if (*hflag == 2) return fail(DMPT_ENONFINITE, std::string(what) + " has a non-finite entry");
+  return DMPT_OK;
+}
+
+// Gershgorin bounds and the normalised S0 of H0 into the context (Algorithm 1
+// initial transform).  No allocation.
+dmpt_status normalise(dmpt_ctx* c, const double* H0) {
+  if (c->check_sym) {
+    dmpt_status r = check_symmetric(H0, c->n, c->dflag, c->hflag, c->stream, "H0");
+    if (r != DMPT_OK) return r;
+  }
+  hipStream_t s = c->stream;
+  HIPCHK(hipMemsetAsync(c->st, 0, sizeof(LayerState), s));
+  HIPCHK(launch_gershgorin(H0, c->n, c->part + kPartGersh, c->st, c->dscal, s));
+  HIPCHK(launch_init_s0(c->prec, H0, c->n, c->np, c->st, c->s_init, s));
+  HIPCHK(hipMemcpyAsync(c->hstate, c->st, sizeof(LayerState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (c->hstate->error) return fail((dmpt_status)c->hstate->error, "non-finite Gershgorin bounds");
+  return DMPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dmpt_default_options(dmpt_options* opt) {
+  if (!opt) return;
+  opt->precision = DMPT_SPLIT_FP16;
+  opt->max_layers = 100;
+  opt->check_symmetry = 0;
+  opt->poll_every = 0;
+  opt->timing = 0;
+}
+
+const char* dmpt_status_str(dmpt_status s) {
+  switch (s) {
+    case DMPT_OK: return "DMPT_OK";
+    case DMPT_EINVAL: return "DMPT_EINVAL";
+    case DMPT_ENOMEM: return "DMPT_ENOMEM";
+    case DMPT_EHIP: return "DMPT_EHIP";
+    case DMPT_ENOCONV: return "DMPT_ENOCONV";
+    case DMPT_ENONFINITE: return "DMPT_ENONFINITE";
+    case DMPT_EASYM: return "DMPT_EASYM";
+    case DMPT_ENOTSUP: return "DMPT_ENOTSUP";
+  }
+  return "DMPT_UNKNOWN";
+}
+
+const char* dmpt_last_error(void) { return g_err.c_str(); }
+
+dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc, int32_t k_max,
+                      const dmpt_options* opt_in, void* stream) {
+  if (!out) return fail(DMPT_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  dmpt_options opt;
+  dmpt_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (!H0) return fail(DMPT_EINVAL, "H0 is NULL");
+  if (N < 1 || N > (1 << 17)) return fail(DMPT_EINVAL, "N out of range");
+  if (Nocc <= 0 || Nocc >= N) return fail(DMPT_EINVAL, "need 0 < Nocc < N");
+  if (k_max < 1 || k_max > kMaxK) return fail(DMPT_EINVAL, "k_max out of [1, DMPT_MAX_K]");
+  if (opt.precision < DMPT_FP64 || opt.precision > DMPT_SPLIT_FP16)
+    return fail(DMPT_ENOTSUP, "unknown precision");
+  if (opt.max_layers <= 0) opt.max_layers = 100;
+  if (opt.max_layers > kMaxLayers) return fail(DMPT_EINVAL, "max_layers above DMPT_MAX_LAYERS");
+
+  dmpt_ctx* c = new dmpt_ctx();  // value-initialised: every pointer NULL
+  c->prec = (dmpt_precision)opt.precision;
+  c->n = N;
+  c->nocc = Nocc;
+  const int tile = product_tile(c->prec);
+  c->np = (N + tile - 1) / tile * tile;
+  c->k_max = k_max;
+  c->max_layers = opt.max_layers;
+  c->check_sym = opt.check_symmetry;
+  c->poll = opt.poll_every > 0 ? opt.poll_every : (c->np >= 2048 ? 1 : 4);
+  c->stream = (hipStream_t)stream;
+
+  auto bail = [&](dmpt_status s, const std::string& m) {
+    ctx_free(c);
+    return fail(s, m);
+  };
+  const size_t eb = elem_bytes(c->prec);
+  const size_t mat = (size_t)c->np * c->np;
+  hipError_t e = hipSuccess;
+  auto get = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = c->mem.get(p, bytes);
+  };
+  get((void**)&c->st, sizeof(LayerState));
+  get(&c->s_init, mat * eb);
+  get(&c->s_master, mat * eb);
+  get(&c->x, mat * eb);
+  if (is_split(c->prec)) {
+    get(&c->s_hi, mat * 2);
+    get(&c->s_lo, mat * 2);
+  }
+  for (int j = 0; j < k_max; ++j) {
+    get(&c->s1buf[j][0], mat * eb);
+    get(&c->s1buf[j][1], mat * eb);
+    if (is_split(c->prec)) {
+      get(&c->s1_hi[j], mat * 2);
+      get(&c->s1_lo[j], mat * 2);
+    }
+  }
+  get((void**)&c->part, kPartTotal * sizeof(double));
+  get((void**)&c->dscal, 16 * sizeof(double));
+  get((void**)&c->dflag, 16 * sizeof(int32_t));
+  const int T = (int)(c->np / tile);
+  for (int k = 1; k <= k_max; ++k) {
+    std::vector<TileItem> items = build_items(T, k);
+    c->n_items[k] = (int)items.size();
+    get((void**)&c->items[k], items.size() * sizeof(TileItem));
+    if (e == hipSuccess)
+      e = hipMemcpy(c->items[k], items.data(), items.size() * sizeof(TileItem),
+                    hipMemcpyHostToDevice);
+  }
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return bail(DMPT_ENOMEM, "device allocation failed");
+  if (e != hipSuccess) return bail(DMPT_EHIP, std::string("allocation: ") + hipGetErrorString(e));
+  if (hipHostMalloc((void**)&c->hstate, sizeof(LayerState), 0) != hipSuccess ||
+      hipHostMalloc((void**)&c->hflag, 16 * sizeof(int32_t), 0) != hipSuccess ||
+      hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), 0) != hipSuccess)
+    return bail(DMPT_ENOMEM, "pinned host allocation failed");
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+    return bail(DMPT_EHIP, "event creation failed");
+  c->timing = opt.timing;
+  if (c->timing)
+    for (int i = 0; i < 2 * c->max_layers; ++i)
+      if (hipEventCreate(&c->pev[i]) != hipSuccess) return bail(DMPT_EHIP, "event creation failed");
+  dmpt_status r = normalise(c, H0);
+  if (r != DMPT_OK) {
+    std::string m = g_err;
+    return bail(r, m);
+  }
+  *out = c;
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_set_hamiltonian(dmpt_ctx* c, const double* H0) {
+  if (!c || !H0) return fail(DMPT_EINVAL, "NULL argument");
+  return normalise(c, H0);
+}
+
+void dmpt_destroy(dmpt_ctx* ctx) { ctx_free(ctx); }
+
+dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, double* P0,
+                          double* const* P1, dmpt_stats* stats) {
+  if (!c) return fail(DMPT_EINVAL, "ctx is NULL");
+  if (k < 1 || k > c->k_max) return fail(DMPT_EINVAL, "k out of [1, k_max]");
+  if (!H1 || !P1) return fail(DMPT_EINVAL, "H1 / P1 array is NULL");
+  for (int j = 0; j < k; ++j)
+    if (!H1[j] || !P1[j]) return fail(DMPT_EINVAL, "NULL H1[j] or P1[j]");
+  hipStream_t s = c->stream;
+  if (c->check_sym)
+    for (int j = 0; j < k; ++j) {
+      dmpt_status r = check_symmetric(H1[j], c->n, c->dflag, c->hflag, s, "H1");
+      if (r != DMPT_OK) return r;
+    }
+  const dmpt_precision prec = c->prec;
+  const int t = lo_shift(prec);
+  const int split = is_split(prec) ? 1 : 0;
+  const int64_t ld = c->np;
+
+  HIPCHK(hipEventRecord(c->ev0, s));
+  HIPCHK(launch_reset_state(c->st, k, c->max_layers, (double)c->nocc, c->n, s));
+  HIPCHK(launch_load_s0(prec, c->s_init, c->s_master, c->s_hi, c->s_lo, ld, t, s));
+  for (int j = 0; j < k; ++j)
+    HIPCHK(launch_init_s1(prec, H1[j], c->n, ld, c->st, j, c->part + kPartMaxabs, c->s1buf[j][0],
+                          c->s1_hi[j], c->s1_lo[j], t, 0.0, s));
+
+  ProductArgs pa;
+  memset(&pa, 0, sizeof(pa));
+  pa.s_hi = split ? c->s_hi : c->s_master;
+  pa.s_lo = c->s_lo;
+  pa.x = c->x;
+  pa.items = c->items[k];
+  pa.n_items = c->n_items[k];
+  pa.state = c->st;
+  pa.ld = ld;
+  pa.lo_shift = t;
+
+  int n = 0;
+  bool stopped = false;
+  while (n < c->max_layers && !stopped) {
+    ++n;
+    const int cur = n & 1, prv = cur ^ 1;
+    for (int j = 0; j < k; ++j) {
+      pa.s1_hi[j] = split ? c->s1_hi[j] : c->s1buf[j][prv];
+      pa.s1_lo[j] = c->s1_lo[j];
+      pa.x1[j] = c->s1buf[j][cur];
+    }
+    if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1)], s));
+    HIPCHK(launch_products(prec, pa, s));
+    if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1) + 1], s));
+    HIPCHK(launch_decide0(prec, c->st, c->x, ld, s));
+    HIPCHK(launch_update(prec, c->st, -1, c->x, c->s_master, c->s_master, c->s_hi, c->s_lo, ld, t,
+                         c->part + kPartFro0, nullptr, s));
+    for (int j = 0; j < k; ++j)
+      HIPCHK(launch_update(prec, c->st, j, c->s1buf[j][cur], c->s1buf[j][prv], c->s1buf[j][cur],
+                           c->s1_hi[j], c->s1_lo[j], ld, t,
+                           c->part + kPartFro1 + (size_t)j * kRedBlocks,
+                           c->part + kPartMax1 + (size_t)j * kRedBlocks, s));
+    HIPCHK(launch_decide1(c->st, c->part + kPartFro0, c->part + kPartFro1, c->part + kPartMax1,
+                          split, t, s));
+    if (n % c->poll == 0 || n == c->max_layers) {
+      HIPCHK(hipMemcpyAsync(c->hflag, &c->st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      stopped = c->hflag[0] != 0;
+    }
+  }
+  if (P0) HIPCHK(launch_copy_out(prec, c->st, -1, c->s_master, c->s_master, ld, P0, c->n, s));
+  for (int j = 0; j < k; ++j)
+    HIPCHK(launch_copy_out(prec, c->st, j, c->s1buf[j][0], c->s1buf[j][1], ld, P1[j], c->n, s));
+  HIPCHK(hipEventRecord(c->ev1, s));
+  if (P0) HIPCHK(launch_trace(P0, c->n, c->dscal, s));
+  for (int j = 0; j < k; ++j) HIPCHK(launch_trace(P1[j], c->n, c->dscal + 1 + j, s));
+  HIPCHK(hipMemcpyAsync(c->hstate, c->st, sizeof(LayerState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->hscal, c->dscal, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const LayerState& h = *c->hstate;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->layers = h.n;
+    stats->d0_layer = h.d0_layer;
+    stats->k = k;
+    stats->converged = h.converged;
+    for (int i = 1; i <= h.n && i <= kMaxLayers; ++i) stats->sigma[i - 1] = (int8_t)h.sigma[i];
+    stats->eps1 = h.eps1;
+    stats->epsN = h.epsN;
+    stats->n_s = h.n_s;
+    stats->idem0 = h.fro0;
+    stats->trace_p0 = P0 ? c->hscal[0] : 0.0;
+    for (int j = 0; j < k; ++j) {
+      stats->d1_layer[j] = h.d1_layer[j];
+      stats->idem1[j] = h.d1_layer[j] > 0 ? h.fro1[j][h.d1_layer[j]] : 0.0;
+      stats->trace_p1[j] = c->hscal[1 + j];
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    stats->ms = ms;
+    stats->x_layers = h.d0_layer > 0 ? h.d0_layer : h.n;
+    if (c->timing) {
+      // launches of layers after the stop return at once; time only layers 1..h.n
+      double tot = 0.0;
+      for (int i = 0; i < h.n && i < n; ++i) {
+        float t_ms = 0.f;
+        hipEventElapsedTime(&t_ms, c->pev[2 * i], c->pev[2 * i + 1]);
+        tot += t_ms;
+      }
+      stats->product_ms = tot;
+      stats->product_launches = std::min(h.n, n);
+    }
+  }
+  if (h.error) return fail((dmpt_status)h.error, "non-finite value or split overflow in a layer");
+  if (!h.converged) return fail(DMPT_ENOCONV, "layer cap reached before every D1 test fired");
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, const double* S1,
+                                double* X, double* X1, void* stream) {
+  if (precision < DMPT_FP64 || precision > DMPT_SPLIT_FP16)
+    return fail(DMPT_ENOTSUP, "unknown precision");
+  if (N < 1 || !S || !X) return fail(DMPT_EINVAL, "bad arguments");
+  if ((S1 == nullptr) != (X1 == nullptr)) return fail(DMPT_EINVAL, "S1 and X1 go together");
+  const dmpt_precision prec = (dmpt_precision)precision;
+  hipStream_t s = (hipStream_t)stream;
+  const int tile = product_tile(prec);
+  const int64_t np = (N + tile - 1) / tile * tile;
+  const size_t mat = (size_t)np * np, eb = elem_bytes(prec);
+  const bool split = is_split(prec);
+  const int t = lo_shift(prec);
+  DevAlloc mem;
+  void *sm = nullptr, *sh = nullptr, *sl = nullptr, *tm = nullptr, *th = nullptr, *tl = nullptr;
+  void *xo = nullptr, *x1o = nullptr, *items = nullptr;
+  double *part = nullptr, *hmax = nullptr;
+  hipError_t e = hipSuccess;
+  auto get = [&](void** p, size_t b) {
+    if (e == hipSuccess) e = mem.get(p, b);
+  };
+  get(&sm, mat * eb);
+  get(&xo, mat * eb);
+  if (split) {
+    get(&sh, mat * 2);
+    get(&sl, mat * 2);
+  }
+  if (S1) {
+    get(&tm, mat * eb);
+    get(&x1o, mat * eb);
+    if (split) {
+      get(&th, mat * 2);
+      get(&tl, mat * 2);
+    }
+  }
+  get((void**)&part, kRedBlocks * sizeof(double));
+  const int T = (int)(np / tile);
+  std::vector<TileItem> it = build_items(T, S1 ? 1 : 0);
+  get(&items, it.size() * sizeof(TileItem));
+  if (e != hipSuccess) {
+    mem.release();
+    return fail(e == hipErrorOutOfMemory ? DMPT_ENOMEM : DMPT_EHIP, "allocation failed");
+  }
+  auto done = [&](dmpt_status st, const std::string& m) {
+    hipStreamSynchronize(s);
+    mem.release();
+    if (hmax) hipHostFree(hmax);
+    return st == DMPT_OK ? DMPT_OK : fail(st, m);
+  };
+  if (hipHostMalloc((void**)&hmax, sizeof(double) * kRedBlocks, 0) != hipSuccess)
+    return done(DMPT_ENOMEM, "pinned allocation failed");
+  if (hipMemcpyAsync(items, it.data(), it.size() * sizeof(TileItem), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return done(DMPT_EHIP, "item upload failed");
+  int e1 = 0;
+  if (S1) {
+    if (launch_maxabs(S1, N, part, s) != hipSuccess ||
+        hipMemcpyAsync(hmax, part, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return done(DMPT_EHIP, "max|S1| failed");
+    double m = 0.0;
+    for (int i = 0; i < kRedBlocks; ++i) m = std::max(m, hmax[i]);
+    e1 = (m > 0.0) ? -ilogb(m) - 4 : 0;
+  }
+  ProductArgs pa;
+  memset(&pa, 0, sizeof(pa));
+  pa.s_hi = split ? sh : sm;
+  pa.s_lo = sl;
+  pa.x = xo;
+  pa.items = (const TileItem*)items;
+  pa.n_items = (int)it.size();
+  pa.state = nullptr;
+  pa.ld = np;
+  pa.lo_shift = t;
+  if (S1) {
+    pa.s1_hi[0] = split ? th : tm;
+    pa.s1_lo[0] = tl;
+    pa.x1[0] = x1o;
+    pa.s1_exp[0] = split ? e1 : 0;
+  }
+  if (launch_from_f64(prec, S, N, np, 0, t, sm, sh, sl, s) != hipSuccess)
+    return done(DMPT_EHIP, "split of S failed");
+  if (S1 && launch_from_f64(prec, S1, N, np, split ? e1 : 0, t, tm, th, tl, s) != hipSuccess)
+    return done(DMPT_EHIP, "split of S1 failed");
+  hipError_t le = launch_products(prec, pa, s);
+  if (le != hipSuccess) return done(DMPT_EHIP, std::string("products: ") + hipGetErrorString(le));
+  if (launch_copy_plain(prec, xo, np, X, N, s) != hipSuccess)
+    return done(DMPT_EHIP, "copy of X failed");
+  if (S1 && launch_copy_plain(prec, x1o, np, X1, N, s) != hipSuccess)
+    return done(DMPT_EHIP, "copy of X1 failed");
+  if (hipStreamSynchronize(s) != hipSuccess) return done(DMPT_EHIP, "synchronize failed");
+  return done(DMPT_OK, "");
+}
+
+dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps, void* stream) {
+  if (!H || !eps || N < 1) return fail(DMPT_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  double *part = nullptr, *dev = nullptr;
+  if (hipMalloc((void**)&part, 3 * 512 * sizeof(double)) != hipSuccess)
+    return fail(DMPT_ENOMEM, "allocation failed");
+  if (hipMalloc((void**)&dev, 2 * sizeof(double)) != hipSuccess) {
+    hipFree(part);
+    return fail(DMPT_ENOMEM, "allocation failed");
+  }
+  hipError_t e = launch_gershgorin(H, N, part, nullptr, dev, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(eps, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(part);
+  hipFree(dev);
+  return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
+}
+
+dmpt_status dmpt_selftest_mfma(int32_t* detail, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* dev = nullptr;
+  int32_t host[kWave];
+  if (hipMalloc((void**)&dev, kWave * sizeof(int32_t)) != hipSuccess)
+    return fail(DMPT_ENOMEM, "allocation failed");
+  hipError_t e = launch_selftest_mfma(dev, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(dev);
+  if (e != hipSuccess) return fail(DMPT_EHIP, hipGetErrorString(e));
+  int32_t bad = 0;
+  for (int i = 0; i < kWave; ++i) bad |= host[i];
+  if (detail) *detail = bad;
+  return bad ? fail(DMPT_ENOTSUP, "MFMA lane layout differs from the kernels' assumption")
+             : DMPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal declarations shared by the HIP translation units of libdmpt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dmpt.h"
+
+namespace dmpt {
+
+// ----------------------------------------------------------------- vectors
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr int kMaxK = DMPT_MAX_K;
+constexpr int kMaxLayers = DMPT_MAX_LAYERS;
+constexpr int kRedBlocks = 1024;  // fixed grid of the reducing elementwise kernels
+
+// Scale of the low part of a split operand: lo = RN((x - hi) * 2^t).
+// FP16 needs it to keep lo out of the subnormal range; BF16 has FP32's
+// exponent range and uses t = 0.
+constexpr int kLoShiftF16 = 11;
+constexpr int kLoShiftBF16 = 0;
+
+// ----------------------------------------------------------------- layer state
+// Scalar state of Algorithms 1-3 kept in device memory so that the layer loop
+// needs no host round trip.  Written only by the single-workgroup decision
+// kernels; read by every kernel of the next steps.
+struct LayerState {
+  // configuration
+  int32_t n_real;            // N
+  int32_t k;                 // number of responses
+  int32_t max_layers;
+  int32_t pad0;
+  double nocc;
+  // progress
+  int32_t n;                 // index of the layer in progress / last run
+  int32_t done;              // 1: every response stopped, cap reached, or error
+  int32_t error;             // dmpt_status of a device-detected error (0 = none)
+  int32_t converged;         // 1: every D1 test fired
+  // zeroth order
+  int32_t d0;                // D0 converged (before or at layer n)
+  int32_t d0_layer;
+  int32_t x_computed;        // X = S^2 was formed at layer n
+  int32_t upd_s0;            // S0 is updated at layer n
+  int32_t d0_now;            // the D0 test fired at layer n
+  int32_t sigma_cur;         // sigma_n
+  double n_s;                // tracked occupation N_S
+  double n_s0;               // Tr S0 of the normalisation layer
+  double fro0;               // ||S - S^2||_F at the D0 layer
+  double eps1, epsN;
+  int32_t sigma[kMaxLayers + 1];   // sigma[n], n = 1..
+  double iderr[kMaxLayers + 1];    // IdErr_n
+  // first order
+  int32_t d1[kMaxK];
+  int32_t d1_layer[kMaxK];
+  int32_t s1_exp_split[kMaxK];     // 2^e scale of the stored S1 hi/lo split (read by the products)
+  int32_t s1_exp_next[kMaxK];      // scale the next update writes the split with
+  double fro1[kMaxK][kMaxLayers + 1];
+  double s1_max[kMaxK];
+};
+
+// One output tile of a layer product.  out = 0: X = S^2; out = 1 + j: X1_j.
+struct TileItem {
+  int16_t out;
+  int16_t pad;
+  int32_t ti, tj;            // tile row/col (ti <= tj)
+};
+
+// Pointers of the layer products.  The product kernels read `state` to skip
+// outputs whose order has converged and to find the S1 split scales.
+struct ProductArgs {
+  const void* s_hi;          // split: 16-bit hi of S; direct forms: S itself
+  const void* s_lo;          // split: 16-bit scaled lo of S
+  const void* s1_hi[kMaxK];
+  const void* s1_lo[kMaxK];
+  void* x;                   // X (FP32 or FP64)
+  void* x1[kMaxK];           // X1_j
+  const TileItem* items;
+  const LayerState* state;   // NULL: compute every item, scales taken from s1_exp
+  int32_t s1_exp[kMaxK];     // used when state == NULL
+  int64_t ld;                // padded leading dimension Np
+  int32_t n_items;
+  int32_t lo_shift;          // t
+};
+
+// ----------------------------------------------------------------- launchers
+// layer products (kernels_gemm.hip)
+int product_tile(dmpt_precision prec);   // output tile edge used by the product kernels
+hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s);
+
+// layer kernels (kernels_layer.hip)
+hipError_t launch_gershgorin(const double* H, int64_t n, double* partial /* 3*512 */,
+                             LayerState* st, double* eps_out, hipStream_t s);
+hipError_t launch_symcheck(const double* H, int64_t n, int32_t* flag, hipStream_t s);
+hipError_t launch_maxabs(const double* H, int64_t n, double* partial, hipStream_t s);
+hipError_t launch_init_s0(dmpt_precision prec, const double* H0, int64_t n, int64_t ld,
+                          const LayerState* st, void* s_init, hipStream_t s);
+hipError_t launch_load_s0(dmpt_precision prec, const void* s_init, void* master, void* hi, void* lo,
+                          int64_t ld, int t, hipStream_t s);
+hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int64_t ld,
+                          LayerState* st, int j, double* partial, void* s1, void* hi, void* lo,
+                          int t, double w_fixed, hipStream_t s);
+hipError_t launch_reset_state(LayerState* st, int k, int max_layers, double nocc, int64_t n,
+                              hipStream_t s);
+hipError_t launch_decide0(dmpt_precision prec, LayerState* st, const void* x, int64_t ld,
+                          hipStream_t s);
+hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, const void* x,
+                         const void* s_old, void* dst, void* hi, void* lo, int64_t ld, int t,
+                         double* pfro, double* pmax, hipStream_t s);
+hipError_t launch_decide1(LayerState* st, const double* pfro0, const double* pfro1,
+                          const double* pmax1, int split, int lo_shift, hipStream_t s);
+hipError_t launch_copy_out(dmpt_precision prec, const LayerState* st, int which, const void* b0,
+                           const void* b1, int64_t ld, double* dst, int64_t n, hipStream_t s);
+hipError_t launch_trace(const double* P, int64_t n, double* out, hipStream_t s);
+hipError_t launch_from_f64(dmpt_precision prec, const double* A, int64_t n, int64_t ld, int e,
+                           int t, void* master, void* hi, void* lo, hipStream_t s);
+hipError_t launch_copy_plain(dmpt_precision prec, const void* src, int64_t ld, double* dst,
+                             int64_t n, hipStream_t s);
+hipError_t launch_selftest_mfma(int32_t* result, hipStream_t s);
+
+}  // namespace dmpt

@@ -1,0 +1,500 @@
+// Layer products of the DNN-SP2-PT network on gfx950 MFMA.
+//
+// One launch forms, for every output tile (ti <= tj) of the upper triangle,
+//   X    = S S                      (zeroth-order activation, Eq. S0 tensor core)
+//   X1_j = S S1_j + S1_j S          (first-order activation, Eqs. FP32S0S1 and
+//                                    S0S1 tensor core, with the symmetry remark
+//                                    that closes Sec. III.C)
+// and mirrors the tile into (tj, ti): every operand and result is symmetric, so
+// each product is read as two row panels that are contiguous along k (an
+// A * B^T form) and only half of the tiles are computed.
+//
+// Split form (prior art: the dual half-precision representation, Eqs. DualMat,
+// DualMat2): a symmetric operand Y is stored as hi = RN16(Y 2^e) and
+// lo = RN16((Y 2^e - hi) 2^t).  With a single FP32 accumulator
+//   acc = (2^t hi_A) hi_B + hi_A lo_B + lo_A hi_B  ( = 2^(t + eA + eB) A B )
+// and the epilogue multiplies by 2^-(t + eA + eB).  The lo*lo term is dropped
+// as in the paper.  The 2^t factor is applied to hi_A in registers (exact).
+#include "dmpt_internal.h"
+
+namespace dmpt {
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int xcd_remap(int b, int g) {
+  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+  // contiguous run of tile items so that the tiles resident on one XCD share
+  // row panels in its L2.
+  const int q = g / kXcds, r = g % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ------------------------------------------------------------------ split form
+template <typename T16> struct Split16;
+
+template <> struct Split16<_Float16> {
+  typedef f16x8 V;
+  static constexpr int kShift = kLoShiftF16;
+  static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ V up(V a) {
+    return a * (_Float16)(float)(1 << kShift);
+  }
+};
+
+template <> struct Split16<__bf16> {
+  typedef bf16x8 V;
+  static constexpr int kShift = kLoShiftBF16;
+  static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ V up(V a) { return a; }  // t = 0
+};
+
+// Resolve the skip flags and the operand scale of one tile item.
+// Returns false when the item has nothing to do.
+__device__ __forceinline__ bool item_active(const ProductArgs& a, const TileItem& it, int* sexp) {
+  const LayerState* st = a.state;
+  if (st) {
+    if (st->done) return false;
+    if (it.out == 0 ? st->d0 : st->d1[it.out - 1]) return false;
+    *sexp = it.out == 0 ? 0 : st->s1_exp_split[it.out - 1];
+  } else {
+    *sexp = it.out == 0 ? 0 : a.s1_exp[it.out - 1];
+  }
+  return true;
+}
+
+template <typename T16, int BM, int BK, int WGM, int WGN, int SWZ>
+__global__ void __launch_bounds__(WGM * WGN * kWave)
+k_products_split(const ProductArgs a) {
+  using S = Split16<T16>;
+  using V = typename S::V;
+  constexpr int NT = WGM * WGN * kWave;
+  constexpr int BN = BM;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / 32, FN = WTN / 32;
+  constexpr int CH = BK / 8;                 // 16-byte chunks per row of a k-tile
+  constexpr int ROWS = 2 * BM + 2 * BN;      // A_hi | A_lo | B_hi | B_lo
+  constexpr int STAGE = ROWS * CH;           // chunks per pipeline stage
+  constexpr int RPL = NT / CH;               // rows covered by one load round
+  constexpr int LOADS = ROWS / RPL;          // load rounds per k-tile
+  static_assert(ROWS % RPL == 0 && BM % RPL == 0, "load rounds must not straddle arrays");
+  static_assert(BK % 16 == 0 && WTM % 32 == 0 && WTN % 32 == 0, "tile shape");
+  extern __shared__ u32x4 lds[];
+
+  const int item_id = xcd_remap(blockIdx.x, gridDim.x);
+  if (item_id >= a.n_items) return;
+  const TileItem it = a.items[item_id];
+  int sexp = 0;
+  if (!item_active(a, it, &sexp)) return;
+
+  const int64_t ld = a.ld;
+  const int j = it.out - 1;
+  const int nprod = it.out == 0 ? 1 : 2;
+  // operand panels per product: [hi_A, lo_A, hi_B, lo_B]
+  const uint16_t* P[2][4];
+  {
+    const uint16_t* sh = (const uint16_t*)a.s_hi;
+    const uint16_t* sl = (const uint16_t*)a.s_lo;
+    if (it.out == 0) {
+      P[0][0] = sh; P[0][1] = sl; P[0][2] = sh; P[0][3] = sl;
+      P[1][0] = sh; P[1][1] = sl; P[1][2] = sh; P[1][3] = sl;
+    } else {
+      const uint16_t* th = (const uint16_t*)a.s1_hi[j];
+      const uint16_t* tl = (const uint16_t*)a.s1_lo[j];
+      P[0][0] = sh; P[0][1] = sl; P[0][2] = th; P[0][3] = tl;
+      P[1][0] = th; P[1][1] = tl; P[1][2] = sh; P[1][3] = sl;
+    }
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int lrow = tid / CH, lch = tid % CH;
+  const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BN;
+  const int kt_per = (int)(ld / BK);
+  const int ktiles = nprod * kt_per;
+
+  u32x4 regs[LOADS];
+  auto gload = [&](int t) {
+    const int p = t / kt_per;
+    const int64_t k0 = (int64_t)(t - p * kt_per) * BK;
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int arr = (i * RPL) / BM;             // compile-time after unrolling
+      const int r = i * RPL - arr * BM + lrow;
+      const int64_t grow = (arr < 2 ? row_a0 : row_b0) + r;
+      const uint16_t* basep = p == 0 ? P[0][arr] : P[1][arr];
+      regs[i] = *(const u32x4*)(basep + grow * ld + k0 + lch * 8);
+    }
+  };
+  auto lstore = [&](int stage) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int R = i * RPL + lrow;
+      lds[stage * STAGE + R * CH + (lch ^ ((R >> SWZ) & (CH - 1)))] = regs[i];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int m = 0; m < FM; ++m)
+#pragma unroll
+    for (int n = 0; n < FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.0f;
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int t = 0; t < ktiles; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < ktiles) gload(t + 1);
+    const u32x4* base = lds + cur * STAGE;
+#pragma unroll
+    for (int kk = 0; kk < BK / 16; ++kk) {
+      const int c = kk * 2 + (lane >> 5);
+      V ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+      for (int m = 0; m < FM; ++m) {
+        const int R = wm * WTM + m * 32 + (lane & 31);
+        const int cc = c ^ ((R >> SWZ) & (CH - 1));
+        ah[m] = __builtin_bit_cast(V, base[R * CH + cc]);
+        al[m] = __builtin_bit_cast(V, base[(R + BM) * CH + cc]);
+      }
+#pragma unroll
+      for (int n = 0; n < FN; ++n) {
+        const int R = 2 * BM + wn * WTN + n * 32 + (lane & 31);
+        const int cc = c ^ ((R >> SWZ) & (CH - 1));
+        bh[n] = __builtin_bit_cast(V, base[R * CH + cc]);
+        bl[n] = __builtin_bit_cast(V, base[(R + BN) * CH + cc]);
+      }
+#pragma unroll
+      for (int m = 0; m < FM; ++m) {
+        const V as = S::up(ah[m]);
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(as, bh[n], acc[m][n]);
+      }
+#pragma unroll
+      for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(ah[m], bl[n], acc[m][n]);
+#pragma unroll
+      for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(al[m], bh[n], acc[m][n]);
+    }
+    if (t + 1 < ktiles) lstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: unscale, store the tile and its mirror image
+  const float scale = ldexpf(1.0f, -(S::kShift + sexp));
+  float* C = (float*)(it.out == 0 ? a.x : a.x1[j]);
+  const bool diag = it.ti == it.tj;
+#pragma unroll
+  for (int m = 0; m < FM; ++m)
+#pragma unroll
+    for (int n = 0; n < FN; ++n) {
+      const int64_t gc = row_b0 + wn * WTN + n * 32 + (lane & 31);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t gr0 = row_a0 + wm * WTM + m * 32 + 8 * g + 4 * (lane >> 5);
+        f32x4 v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = acc[m][n][4 * g + r] * scale;
+        if (!diag) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) C[(gr0 + r) * ld + gc] = v[r];
+          *(f32x4*)(C + gc * ld + gr0) = v;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t gr = gr0 + r;
+            if (gr <= gc) C[gr * ld + gc] = v[r];
+            if (gr < gc) C[gc * ld + gr] = v[r];
+          }
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------------ direct forms
+template <typename T> struct Direct;
+// Output element r of lane l sits in column l % 16 and in row
+//   4 (l / 16) + r   for the f32 form,
+//   l / 16 + 4 r     for the f64 form (rows interleaved).
+template <> struct Direct<float> {
+  typedef f32x4 Acc;
+  static __device__ __forceinline__ Acc mma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <> struct Direct<double> {
+  typedef f64x4 Acc;
+  static __device__ __forceinline__ Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+// Same tiling with one operand copy per matrix and the 16x16x4 MFMA: a lane
+// reads one 16-byte chunk (E consecutive k) per fragment and issues E MFMAs,
+// the e-th taking element e; A and B use the same (lane group, e) -> k map.
+template <typename T, int BM, int BK, int WGM, int WGN, int SWZ>
+__global__ void __launch_bounds__(WGM * WGN * kWave)
+k_products_direct(const ProductArgs a) {
+  using D = Direct<T>;
+  using Acc = typename D::Acc;
+  constexpr int E = 16 / sizeof(T);
+  constexpr int NT = WGM * WGN * kWave;
+  constexpr int BN = BM;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int CH = BK / E;
+  constexpr int ROWS = BM + BN;              // A | B
+  constexpr int STAGE = ROWS * CH;
+  constexpr int RPL = NT / CH;
+  constexpr int LOADS = ROWS / RPL;
+  static_assert(ROWS % RPL == 0 && BM % RPL == 0, "load rounds must not straddle arrays");
+  static_assert(CH % 4 == 0, "k-tile must hold a multiple of 4 chunks");
+  extern __shared__ u32x4 lds[];
+
+  const int item_id = xcd_remap(blockIdx.x, gridDim.x);
+  if (item_id >= a.n_items) return;
+  const TileItem it = a.items[item_id];
+  int sexp = 0;
+  if (!item_active(a, it, &sexp)) return;
+  (void)sexp;  // direct forms store S1 unscaled
+
+  const int64_t ld = a.ld;
+  const int j = it.out - 1;
+  const int nprod = it.out == 0 ? 1 : 2;
+  const T* P[2][2];
+  {
+    const T* s = (const T*)a.s_hi;
+    if (it.out == 0) {
+      P[0][0] = s; P[0][1] = s; P[1][0] = s; P[1][1] = s;
+    } else {
+      const T* s1 = (const T*)a.s1_hi[j];
+      P[0][0] = s; P[0][1] = s1; P[1][0] = s1; P[1][1] = s;
+    }
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int lrow = tid / CH, lch = tid % CH;
+  const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BN;
+  const int kt_per = (int)(ld / BK);
+  const int ktiles = nprod * kt_per;
+
+  u32x4 regs[LOADS];
+  auto gload = [&](int t) {
+    const int p = t / kt_per;
+    const int64_t k0 = (int64_t)(t - p * kt_per) * BK;
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int arr = (i * RPL) / BM;             // compile-time after unrolling
+      const int r = i * RPL - arr * BM + lrow;
+      const int64_t grow = (arr == 0 ? row_a0 : row_b0) + r;
+      const T* basep = p == 0 ? P[0][arr] : P[1][arr];
+      regs[i] = *(const u32x4*)(basep + grow * ld + k0 + lch * E);
+    }
+  };
+  auto lstore = [&](int stage) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int R = i * RPL + lrow;
+      lds[stage * STAGE + R * CH + (lch ^ ((R >> SWZ) & (CH - 1)))] = regs[i];
+    }
+  };
+
+  Acc acc[FM][FN];
+#pragma unroll
+  for (int m = 0; m < FM; ++m)
+#pragma unroll
+    for (int n = 0; n < FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][n][r] = (T)0;
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int t = 0; t < ktiles; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < ktiles) gload(t + 1);
+    const u32x4* base = lds + cur * STAGE;
+#pragma unroll
+    for (int kk = 0; kk < CH / 4; ++kk) {
+      const int c = kk * 4 + (lane >> 4);
+      u32x4 af[FM], bf[FN];
+#pragma unroll
+      for (int m = 0; m < FM; ++m) {
+        const int R = wm * WTM + m * 16 + (lane & 15);
+        af[m] = base[R * CH + (c ^ ((R >> SWZ) & (CH - 1)))];
+      }
+#pragma unroll
+      for (int n = 0; n < FN; ++n) {
+        const int R = BM + wn * WTN + n * 16 + (lane & 15);
+        bf[n] = base[R * CH + (c ^ ((R >> SWZ) & (CH - 1)))];
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+#pragma unroll
+        for (int m = 0; m < FM; ++m) {
+          typedef T TV __attribute__((ext_vector_type(E)));
+          const T av = __builtin_bit_cast(TV, af[m])[e];
+#pragma unroll
+          for (int n = 0; n < FN; ++n) {
+            const T bv = __builtin_bit_cast(TV, bf[n])[e];
+            acc[m][n] = D::mma(av, bv, acc[m][n]);
+          }
+        }
+      }
+    }
+    if (t + 1 < ktiles) lstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  T* C = (T*)(it.out == 0 ? a.x : a.x1[j]);
+  const bool diag = it.ti == it.tj;
+#pragma unroll
+  for (int m = 0; m < FM; ++m)
+#pragma unroll
+    for (int n = 0; n < FN; ++n) {
+      const int64_t gc = row_b0 + wn * WTN + n * 16 + (lane & 15);
+      const int64_t gr0 = row_a0 + wm * WTM + m * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gr = gr0 + D::row(lane, r);
+        const T v = acc[m][n][r];
+        if (!diag || gr <= gc) C[gr * ld + gc] = v;
+        if (!diag || gr < gc) C[gc * ld + gr] = v;
+      }
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+// Tile configurations (edge, k-tile, wave grid, LDS swizzle shift).
+constexpr int kSplitBM = 256, kSplitBK = 32, kSplitWGM = 2, kSplitWGN = 4, kSplitSWZ = 2;
+constexpr int kDirBM = 128, kDirWGM = 2, kDirWGN = 2, kDirSWZ = 1;
+constexpr int kDirBK32 = 32, kDirBK64 = 16;
+
+int product_tile(dmpt_precision prec) {
+  return (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16) ? kSplitBM : kDirBM;
+}
+
+template <typename K>
+static hipError_t launch_one(K kernel, int threads, size_t lds_bytes, const ProductArgs& a,
+                             hipStream_t s) {
+  static_assert(sizeof(ProductArgs) < 4096, "kernel argument block");
+  hipError_t e = hipFuncSetAttribute((const void*)kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  if (a.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kernel, dim3(a.n_items), dim3(threads), lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s) {
+  if (a.ld % product_tile(prec) != 0) return hipErrorInvalidValue;
+  switch (prec) {
+    case DMPT_SPLIT_FP16: {
+      constexpr size_t lds = 2 * (4 * kSplitBM) * (kSplitBK / 8) * 16;
+      return launch_one(k_products_split<_Float16, kSplitBM, kSplitBK, kSplitWGM, kSplitWGN, kSplitSWZ>,
+                        kSplitWGM * kSplitWGN * kWave, lds, a, s);
+    }
+    case DMPT_SPLIT_BF16: {
+      constexpr size_t lds = 2 * (4 * kSplitBM) * (kSplitBK / 8) * 16;
+      return launch_one(k_products_split<__bf16, kSplitBM, kSplitBK, kSplitWGM, kSplitWGN, kSplitSWZ>,
+                        kSplitWGM * kSplitWGN * kWave, lds, a, s);
+    }
+    case DMPT_FP32: {
+      constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK32 / 4) * 16;
+      return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN, kDirSWZ>,
+                        kDirWGM * kDirWGN * kWave, lds, a, s);
+    }
+    case DMPT_FP64: {
+      constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK64 / 2) * 16;
+      return launch_one(k_products_direct<double, kDirBM, kDirBK64, kDirWGM, kDirWGN, kDirSWZ>,
+                        kDirWGM * kDirWGN * kWave, lds, a, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ MFMA layout self-test
+// Small integer operands (exact in every format); each lane compares the
+// elements it holds under the assumed output layout with a direct sum.
+__device__ __forceinline__ int ta(int m, int k) { return ((m * 7 + k * 3) % 5) - 2; }
+__device__ __forceinline__ int tb(int k, int n) { return ((k * 5 + n * 11) % 5) - 2; }
+
+__global__ void k_selftest_mfma(int32_t* out) {
+  const int l = threadIdx.x;
+  int bad = 0;
+  {  // f16 32x32x16: A row l%32, k = 8*(l/32)+e ; B col l%32, same k
+    f16x8 av, bv;
+    for (int e = 0; e < 8; ++e) {
+      av[e] = (_Float16)(float)ta(l & 31, 8 * (l >> 5) + e);
+      bv[e] = (_Float16)(float)tb(8 * (l >> 5) + e, l & 31);
+    }
+    f32x16 c = {};
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, c, 0, 0, 0);
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3), col = l & 31;
+      int ref = 0;
+      for (int k = 0; k < 16; ++k) ref += ta(row, k) * tb(k, col);
+      if (c[r] != (float)ref) bad |= 1;
+    }
+  }
+  {  // bf16 32x32x16
+    bf16x8 av, bv;
+    for (int e = 0; e < 8; ++e) {
+      av[e] = (__bf16)(float)ta(l & 31, 8 * (l >> 5) + e);
+      bv[e] = (__bf16)(float)tb(8 * (l >> 5) + e, l & 31);
+    }
+    f32x16 c = {};
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3), col = l & 31;
+      int ref = 0;
+      for (int k = 0; k < 16; ++k) ref += ta(row, k) * tb(k, col);
+      if (c[r] != (float)ref) bad |= 2;
+    }
+  }
+  {  // f32 16x16x4: A row l%16, k = l/16 ; out row 4*(l/16)+r, col l%16
+    f32x4 c = {};
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32((float)ta(l & 15, l >> 4), (float)tb(l >> 4, l & 15), c,
+                                             0, 0, 0);
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * (l >> 4) + r, col = l & 15;
+      int ref = 0;
+      for (int k = 0; k < 4; ++k) ref += ta(row, k) * tb(k, col);
+      if (c[r] != (float)ref) bad |= 4;
+    }
+  }
+  {  // f64 16x16x4: out row l/16 + 4r, col l%16
+    f64x4 c = {};
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ta(l & 15, l >> 4), (double)tb(l >> 4, l & 15),
+                                             c, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) {
+      const int row = (l >> 4) + 4 * r, col = l & 15;
+      int ref = 0;
+      for (int k = 0; k < 4; ++k) ref += ta(row, k) * tb(k, col);
+      if (c[r] != (double)ref) bad |= 8;
+    }
+  }
+  out[l] = bad;
+}
+
+hipError_t launch_selftest_mfma(int32_t* result, hipStream_t s) {
+  hipLaunchKernelGGL(k_selftest_mfma, dim3(1), dim3(kWave), 0, s, result);
+  return hipGetLastError();
+}
+
+}  // namespace dmpt

@@ -1,0 +1,167 @@
+"""End-to-end parity of the HIP DNN-SP2-PT path with the FP64 oracle.
+
+Bars: the FP64 form within 1e-10 and the split / FP32 forms within 1e-3 in
+relative Frobenius norm for P0 and every P1_k; the FP64 form also follows the
+dense FP64 recursion's sigma sequence up to D0 convergence."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SPLIT_TOL = 1e-3
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_2203_09621_amd as dm
+    return dm
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _solve(dm, p, precision, **kw):
+    P0, P1s, st = dm.solve(_cuda(p.H0), [_cuda(h) for h in p.H1], p.nocc, precision=precision, **kw)
+    return P0.cpu().numpy(), [q.cpu().numpy() for q in P1s], st
+
+
+def _errors(p, P0, P1s):
+    from oracle import exact
+    r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+    return exact.rel_fro(P0, r0), [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    from workloads import config1
+    return config1()
+
+
+def test_config1_fp64_parity_and_sigma(dm, c1):
+    from oracle import sp2pt
+    P0, P1s, st = _solve(dm, c1, "fp64")
+    e0, e1 = _errors(c1, P0, P1s)
+    print(f"config1 fp64: layers={st['layers']} d0={st['d0_layer']} d1={st['d1_layer']} "
+          f"err P0={e0:.2e} P1={e1[0]:.2e}", flush=True)
+    assert st["converged"]
+    assert e0 < FP64_TOL and e1[0] < FP64_TOL
+    _, _, ref = sp2pt.run(c1.H0, c1.H1, c1.nocc)
+    d0 = min(ref["d0_layer"], st["d0_layer"])
+    assert st["sigma"][:d0 - 1] == ref["sigma"][:d0 - 1]
+    assert abs(st["d0_layer"] - ref["d0_layer"]) <= 1
+    assert abs(st["trace_p0"] - c1.nocc) < 1e-9 and abs(st["trace_p1"][0]) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_fp16", "split_bf16"])
+def test_config1_reduced_precision(dm, c1, precision):
+    P0, P1s, st = _solve(dm, c1, precision)
+    e0, e1 = _errors(c1, P0, P1s)
+    print(f"config1 {precision}: layers={st['layers']} d0={st['d0_layer']} d1={st['d1_layer']} "
+          f"err P0={e0:.2e} P1={e1[0]:.2e}", flush=True)
+    assert st["converged"]
+    assert e0 < SPLIT_TOL and e1[0] < SPLIT_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_fp16", "split_bf16", "fp32"])
+def test_ragged_three_diagonal_perturbations(dm, precision):
+    """N = 1000 (not a tile multiple), three coordinate perturbations (config 2 shape)."""
+    from workloads import config2
+    p = config2(n=1000)
+    P0, P1s, st = _solve(dm, p, precision)
+    e0, e1 = _errors(p, P0, P1s)
+    print(f"N=1000 k=3 {precision}: layers={st['layers']} d0={st['d0_layer']} "
+          f"d1={st['d1_layer']} err P0={e0:.2e} P1={[f'{x:.2e}' for x in e1]}", flush=True)
+    tol = FP64_TOL if precision == "fp64" else SPLIT_TOL
+    assert st["converged"]
+    assert e0 < tol and max(e1) < tol
+
+
+def test_banded_small(dm):
+    """Banded H0 (config 3 construction) at N = 768, split FP16."""
+    from workloads import banded_gapped_problem
+    p = banded_gapped_problem(768, 384, 0.2, 77, block=64)
+    P0, P1s, st = _solve(dm, p, "split_fp16")
+    e0, e1 = _errors(p, P0, P1s)
+    print(f"banded N=768: layers={st['layers']} err P0={e0:.2e} P1={e1[0]:.2e}", flush=True)
+    assert st["converged"] and e0 < SPLIT_TOL and e1[0] < SPLIT_TOL
+
+
+def test_repeat_is_bitwise_deterministic(dm, c1):
+    a = _solve(dm, c1, "split_fp16")
+    b = _solve(dm, c1, "split_fp16")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1][0], b[1][0])
+    assert a[2]["sigma"] == b[2]["sigma"]
+
+
+def test_context_reuse_two_responses(dm):
+    """One dmpt_init, two dmpt_response calls with different k."""
+    from oracle import exact
+    from workloads import config2
+    p = config2(n=300)
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=3, precision="split_fp16")
+    try:
+        _, P1a, _ = dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+        _, P1b, _ = dm.dmpt_response(ctx, [_cuda(h) for h in p.H1])
+    finally:
+        dm.dmpt_destroy(ctx)
+    r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+    assert exact.rel_fro(P1a[0].cpu().numpy(), r1s[0]) < SPLIT_TOL
+    for a, b in zip(P1b, r1s):
+        assert exact.rel_fro(a.cpu().numpy(), b) < SPLIT_TOL
+
+
+# ------------------------------------------------------------------ error paths
+def test_invalid_arguments(dm, c1):
+    import torch
+    h0 = _cuda(c1.H0)
+    for nocc in (0, c1.N, -3):
+        with pytest.raises(dm.DmptError) as ei:
+            dm.dmpt_init(h0, nocc)
+        assert ei.value.status == -1
+    with pytest.raises(dm.DmptError) as ei:
+        dm.dmpt_init(h0, 10, k_max=9)
+    assert ei.value.status == -1
+    with pytest.raises(TypeError):
+        dm.dmpt_init(h0.float(), 10)
+    del torch
+
+
+def test_asymmetric_input_rejected(dm, c1):
+    h = c1.H0.copy()
+    h[3, 5] += 1e-9
+    with pytest.raises(dm.DmptError) as ei:
+        dm.solve(_cuda(h), [_cuda(c1.H1[0])], c1.nocc, check_symmetry=True)
+    assert ei.value.status == -6
+
+
+def test_nonfinite_perturbation(dm, c1):
+    h1 = c1.H1[0].copy()
+    h1[2, 2] = np.nan
+    with pytest.raises(dm.DmptError) as ei:
+        dm.solve(_cuda(c1.H0), [_cuda(h1)], c1.nocc, precision="split_fp16")
+    assert ei.value.status == -5
+
+
+def test_layer_cap(dm, c1):
+    with pytest.raises(dm.DmptError) as ei:
+        dm.solve(_cuda(c1.H0), [_cuda(c1.H1[0])], c1.nocc, precision="fp64", max_layers=5)
+    assert ei.value.status == -4
+    assert ei.value.stats["layers"] == 5 and not ei.value.stats["converged"]
+
+
+def test_diagonal_h0_terminates(dm):
+    """Noise-free FP64 input: the D1 test must still stop (exact-zero rule)."""
+    from oracle import exact
+    rng = np.random.default_rng(2)
+    n = 130
+    e = np.concatenate([rng.uniform(-3, -0.5, 60), rng.uniform(0.5, 3, 70)])
+    h1 = rng.normal(size=(n, n)) * 0.01
+    h1 = np.triu(h1) + np.triu(h1, 1).T
+    P0, P1s, st = dm.solve(_cuda(np.diag(e)), [_cuda(h1)], 60, precision="fp64")
+    assert st["converged"]
+    assert exact.rel_fro(P1s[0].cpu().numpy(), exact.density_response(np.diag(e), h1, 60)) < 1e-9

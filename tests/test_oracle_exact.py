@@ -116,6 +116,15 @@ def test_factored_solution_equals_eigh():
         assert exact.rel_fro(b, a) < 1e-10
 
 
+def test_brickwall_factored_solution_equals_eigh():
+    p = banded_gapped_problem(512, 256, 0.2, 41, block=64, h1="dense", k=1)
+    p0a, p1a = exact.solve(p.H0, p.H1, p.nocc)
+    p0b, p1b = exact.solve_from_brickwall(p.basis.e, p.basis.layers, p.basis.layer_offsets(),
+                                          p.basis.block, p.H1, p.nocc)
+    assert exact.rel_fro(p0b, p0a) < 1e-12
+    assert exact.rel_fro(p1b[0], p1a[0]) < 1e-10
+
+
 def test_gershgorin_encloses_spectrum():
     p = small(n=40, seed=9)
     e1, en = exact.gershgorin(p.H0)

@@ -69,6 +69,8 @@ typedef struct {
   int32_t poll_every;      /* host checks the device stop flag every this many layers (0 = auto) */
   int32_t timing;          /* nonzero: time every layer-product launch with hipEvents on the
                               context's stream (dmpt_stats.product_ms / product_launches) */
+  int32_t ckpt_every;      /* > 0: dmpt_response keeps (S, S1) every this many layers so that
+                              dmpt_adjoint can run; 0 (default): no adjoint workspace */
 } dmpt_options;
 
 typedef struct {
@@ -116,6 +118,19 @@ dmpt_status dmpt_set_hamiltonian(dmpt_ctx* ctx, const double* H0);
  * layer).  `st` may be NULL. */
 dmpt_status dmpt_response(dmpt_ctx* ctx, const double* const* H1, int32_t k, double* P0,
                           double* const* P1, dmpt_stats* st);
+
+/* Reverse mode of the layer recursion for L = sum_j Tr(P1_j W_j), applied to
+ * the most recent successful dmpt_response of this context (same k, k <= 3;
+ * the context needs ckpt_every > 0).  W[j] (host array of device FP64 N x N)
+ * is the upstream gradient dL/dP1_j; it is symmetrised.  Writes the symmetric
+ * gradients dH0 = dL/dH0 and dH1[j] = dL/dH1_j (device FP64 N x N, with
+ * dL = <G, dH> for symmetric dH).  The forward is recomputed from the
+ * checkpoints segment by segment with the recorded sigma sequence, scales
+ * and stop layers (no decision is taken again); the products of the reverse
+ * layers run in FP32 MFMA (FP64 for an FP64 context).  The Gershgorin bounds
+ * are treated as constants.  Errors: EINVAL, EHIP. */
+dmpt_status dmpt_adjoint(dmpt_ctx* ctx, const double* const* W, int32_t k, double* dH0,
+                         double* const* dH1, dmpt_stats* st);
 
 /* Release the context and its workspace.  NULL is allowed. */
 void dmpt_destroy(dmpt_ctx* ctx);

@@ -22,14 +22,15 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
-           "dmpt_destroy",
+           "dmpt_adjoint", "dmpt_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
            "dmpt_selftest_mfma"]
 
 
 class DmptOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_layers", c_int32),
-                ("check_symmetry", c_int32), ("poll_every", c_int32), ("timing", c_int32)]
+                ("check_symmetry", c_int32), ("poll_every", c_int32), ("timing", c_int32),
+                ("ckpt_every", c_int32)]
 
 
 class DmptStats(ctypes.Structure):
@@ -76,6 +77,9 @@ def _load():
     lib.dmpt_response.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
                                   POINTER(c_void_p), POINTER(DmptStats)]
     lib.dmpt_response.restype = c_int32
+    lib.dmpt_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
+                                 POINTER(c_void_p), POINTER(DmptStats)]
+    lib.dmpt_adjoint.restype = c_int32
     lib.dmpt_destroy.argtypes = [c_void_p]
     lib.dmpt_destroy.restype = None
     lib.dmpt_status_str.argtypes = [c_int32]
@@ -134,9 +138,10 @@ def default_options() -> DmptOptions:
 # ---------------------------------------------------------------- entry points
 def dmpt_init(H0, nocc: int, k_max: int = 1, precision: str = "split_fp16",
               max_layers: int = 100, check_symmetry: bool = False, poll_every: int = 0,
-              timing: bool = False, stream=None) -> c_void_p:
+              timing: bool = False, ckpt_every: int = 0, stream=None) -> c_void_p:
     """dmpt_init: Gershgorin bounds and the normalised S0 of H0 (device FP64)."""
     o = default_options()
+    o.ckpt_every = int(ckpt_every)
     o.precision = PRECISION[precision]
     o.max_layers = max_layers
     o.check_symmetry = int(check_symmetry)
@@ -171,6 +176,22 @@ def dmpt_response(ctx: c_void_p, H1s, P0=None, P1s=None):
     _check(status, stats)
     del n
     return P0, P1s, stats
+
+
+def dmpt_adjoint(ctx: c_void_p, Ws, dH0=None, dH1s=None):
+    """dmpt_adjoint: gradients of L = sum_k Tr(P1_k W_k) for the last response.
+    Returns (dL/dH0, [dL/dH1_k], stats)."""
+    torch = _torch()
+    k = len(Ws)
+    if dH0 is None:
+        dH0 = torch.empty_like(Ws[0])
+    if dH1s is None:
+        dH1s = [torch.empty_like(w) for w in Ws]
+    w_arr = (c_void_p * k)(*[_dev(w, "W").value for w in Ws])
+    g_arr = (c_void_p * k)(*[_dev(g, "dH1").value for g in dH1s])
+    st = DmptStats()
+    _check(LIB.dmpt_adjoint(ctx, w_arr, k, _dev(dH0, "dH0"), g_arr, byref(st)))
+    return dH0, dH1s, st.as_dict()
 
 
 def dmpt_destroy(ctx: c_void_p) -> None:
@@ -210,3 +231,34 @@ def solve(H0, H1s, nocc: int, precision: str = "split_fp16", max_layers: int = 1
         return dmpt_response(ctx, H1s)
     finally:
         dmpt_destroy(ctx)
+
+
+def response_function():
+    """torch.autograd.Function: P1 = DMPTResponse.apply(H0, H1, nocc, precision, ckpt_every).
+    Its backward calls dmpt_adjoint; gradients follow the symmetric convention
+    (dL = <G, dH> for symmetric dH)."""
+    torch = _torch()
+
+    class DMPTResponse(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, H0, H1, nocc, precision="split_bf16", ckpt_every=8):
+            ctx = dmpt_init(H0.detach().contiguous(), nocc, k_max=1, precision=precision,
+                            ckpt_every=ckpt_every)
+            try:
+                _, (P1,), _ = dmpt_response(ctx, [H1.detach().contiguous()])
+            except Exception:
+                dmpt_destroy(ctx)
+                raise
+            fctx.dmpt = ctx
+            return P1
+
+        @staticmethod
+        def backward(fctx, gP1):
+            try:
+                dH0, (dH1,), _ = dmpt_adjoint(fctx.dmpt, [gP1.contiguous()])
+            finally:
+                dmpt_destroy(fctx.dmpt)
+                fctx.dmpt = None
+            return dH0, dH1, None, None, None
+
+    return DMPTResponse

@@ -63,6 +63,7 @@ struct LayerState {
   int32_t s1_exp_next[kMaxK];      // scale the next update writes the split with
   double fro1[kMaxK][kMaxLayers + 1];
   double s1_max[kMaxK];
+  int32_t s1_exp_hist[kMaxK][kMaxLayers + 1];   // split scale S1_n was written with
 };
 
 // One output tile of a layer product.  out = 0: X = S^2; out = 1 + j: X1_j.
@@ -81,10 +82,12 @@ struct ProductArgs {
   const void* s1_lo[kMaxK];
   void* x;                   // X (FP32 or FP64)
   void* x1[kMaxK];           // X1_j
+  const void* a_op[kMaxK];    // direct forms: A operand of output 1 + j (NULL: S)
   const TileItem* items;
   const LayerState* state;   // NULL: compute every item, scales taken from s1_exp
   int32_t s1_exp[kMaxK];     // used when state == NULL
-  int64_t ld;                // padded leading dimension Np
+  int64_t ld;                // row stride of every matrix (elements, >= kdim)
+  int64_t kdim;              // padded size Np: rows, columns and the k extent
   int32_t n_items;
   int32_t lo_shift;          // t
 };
@@ -99,29 +102,45 @@ hipError_t launch_gershgorin(const double* H, int64_t n, double* partial /* 3*51
                              LayerState* st, double* eps_out, hipStream_t s);
 hipError_t launch_symcheck(const double* H, int64_t n, int32_t* flag, hipStream_t s);
 hipError_t launch_maxabs(const double* H, int64_t n, double* partial, hipStream_t s);
-hipError_t launch_init_s0(dmpt_precision prec, const double* H0, int64_t n, int64_t ld,
-                          const LayerState* st, void* s_init, hipStream_t s);
+// Matrices in the workspace have `rows` = Np rows and row stride `ld` >= Np;
+// the columns [Np, ld) and every entry outside the N x N block hold zero.
+hipError_t launch_init_s0(dmpt_precision prec, const double* H0, int64_t n, int64_t rows,
+                          int64_t ld, const LayerState* st, void* s_init, hipStream_t s);
 hipError_t launch_load_s0(dmpt_precision prec, const void* s_init, void* master, void* hi, void* lo,
-                          int64_t ld, int t, hipStream_t s);
-hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int64_t ld,
-                          LayerState* st, int j, double* partial, void* s1, void* hi, void* lo,
-                          int t, double w_fixed, hipStream_t s);
+                          int64_t rows, int64_t ld, int t, hipStream_t s);
+hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int64_t rows,
+                          int64_t ld, LayerState* st, int j, double* partial, void* s1, void* hi,
+                          void* lo, int t, double w_fixed, hipStream_t s);
 hipError_t launch_reset_state(LayerState* st, int k, int max_layers, double nocc, int64_t n,
                               hipStream_t s);
 hipError_t launch_decide0(dmpt_precision prec, LayerState* st, const void* x, int64_t ld,
                           hipStream_t s);
 hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, const void* x,
-                         const void* s_old, void* dst, void* hi, void* lo, int64_t ld, int t,
+                         const void* s_old, void* dst, void* hi, void* lo, int64_t elems, int t,
                          double* pfro, double* pmax, hipStream_t s);
 hipError_t launch_decide1(LayerState* st, const double* pfro0, const double* pfro1,
                           const double* pmax1, int split, int lo_shift, hipStream_t s);
 hipError_t launch_copy_out(dmpt_precision prec, const LayerState* st, int which, const void* b0,
                            const void* b1, int64_t ld, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_trace(const double* P, int64_t n, double* out, hipStream_t s);
-hipError_t launch_from_f64(dmpt_precision prec, const double* A, int64_t n, int64_t ld, int e,
-                           int t, void* master, void* hi, void* lo, hipStream_t s);
+hipError_t launch_from_f64(dmpt_precision prec, const double* A, int64_t n, int64_t rows,
+                           int64_t ld, int e, int t, void* master, void* hi, void* lo,
+                           hipStream_t s);
 hipError_t launch_copy_plain(dmpt_precision prec, const void* src, int64_t ld, double* dst,
                              int64_t n, hipStream_t s);
+
+// adjoint of the layer recursion (kernels_adjoint.hip)
+hipError_t launch_replay_state(const LayerState* fwd, LayerState* rep, int n, hipStream_t s);
+hipError_t launch_resplit(dmpt_precision prec, const LayerState* fwd, int j, int layer,
+                          const void* master, void* hi, void* lo, int64_t elems, int t,
+                          hipStream_t s);
+hipError_t launch_adj_seed(dmpt_precision prec, const double* W, int64_t n, int64_t rows,
+                           int64_t ld, void* dst, hipStream_t s);
+hipError_t launch_adj_update(dmpt_precision prec, const LayerState* fwd, int layer, int k,
+                             const void* t2, void* sh, const void* const* t1, void* const* sh1,
+                             const void* const* t3, int64_t elems, hipStream_t s);
+hipError_t launch_adj_out(dmpt_precision prec, const LayerState* fwd, const void* src, int64_t ld,
+                          double* dst, int64_t n, hipStream_t s);
 hipError_t launch_selftest_mfma(int32_t* result, hipStream_t s);
 
 }  // namespace dmpt

@@ -1,0 +1,193 @@
+// Adjoint (reverse mode) of the DNN-SP2-PT layer recursion for
+// L = sum_k Tr(P1_k W_k).
+//
+// Forward layer n (sigma_n and the update flags fixed by the forward pass):
+//   S1_n = sigma (S S1 + S1 S) + (1 - sigma) S1        (if response k is updated)
+//   S_n  = sigma S^2 + (1 - sigma) S                   (if S is updated)
+// with S = S_{n-1}, S1 = S1_{n-1}.  For symmetric matrices the adjoints are
+//   Sh1_{n-1} = sigma (S Sh1 + Sh1 S) + (1 - sigma) Sh1                 (S1 updated)
+//   Sh_{n-1}  = [sigma (S Sh + Sh S) + (1 - sigma) Sh]_(S updated)
+//             + sum_k [sigma (Sh1_k S1_k + S1_k Sh1_k)]_(S1_k updated)
+// seeded with Sh1_k = W_k (symmetrised) at the layer that produced P1_k and
+// Sh = 0.  The normalisation layer gives dL/dH1_k = -Sh1_k,0/(eps_N - eps_1)
+// and dL/dH0 = -Sh_0/(eps_N - eps_1); the Gershgorin bounds are treated as
+// constants (the limits P0 and P1 do not depend on them).
+#include "dmpt_internal.h"
+
+namespace dmpt {
+
+constexpr int kBlkA = 256;
+
+template <typename T16> struct Conv16;
+template <> struct Conv16<_Float16> {
+  static __device__ __forceinline__ uint16_t to(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+  static __device__ __forceinline__ float from(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+};
+template <> struct Conv16<__bf16> {
+  static __device__ __forceinline__ uint16_t to(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+  static __device__ __forceinline__ float from(uint16_t b) { return (float)__builtin_bit_cast(__bf16, b); }
+};
+
+// State for replaying forward layer n during recomputation: the sigma and
+// the update flags the forward pass took, and the S1 split scales it used.
+// No decision is taken again.
+__global__ void k_replay_state(const LayerState* f, LayerState* r, int n) {
+  if (threadIdx.x != 0) return;
+  r->n = n;
+  r->k = f->k;
+  r->n_real = f->n_real;
+  r->done = 0;
+  r->error = 0;
+  const int d0l = f->d0_layer > 0 ? f->d0_layer : (1 << 30);
+  r->d0 = n >= d0l ? 1 : 0;          // X is needed only while S is updated
+  r->upd_s0 = n < d0l ? 1 : 0;
+  r->x_computed = 0;
+  r->d0_now = 0;
+  r->sigma_cur = f->sigma[n];
+  for (int j = 0; j < kMaxK; ++j) {
+    const int d1l = (j < f->k && f->d1_layer[j] > 0) ? f->d1_layer[j] : (j < f->k ? (1 << 30) : 0);
+    r->d1[j] = n >= d1l ? 1 : 0;
+    r->s1_exp_split[j] = f->s1_exp_hist[j][n - 1];
+    r->s1_exp_next[j] = f->s1_exp_hist[j][n];
+  }
+}
+
+hipError_t launch_replay_state(const LayerState* fwd, LayerState* rep, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay_state, dim3(1), dim3(kWave), 0, s, fwd, rep, n);
+  return hipGetLastError();
+}
+
+// hi/lo of a restored S1 (j >= 0, scale of layer `layer`) or S (j < 0, scale 1).
+template <typename T16>
+__global__ void __launch_bounds__(kBlkA) k_resplit(const LayerState* f, int j, int layer,
+                                                  const float* m, uint16_t* hi, uint16_t* lo,
+                                                  int64_t elems, int t) {
+  const int e = j >= 0 ? f->s1_exp_hist[j][layer] : 0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlkA + threadIdx.x; q < elems;
+       q += (int64_t)gridDim.x * kBlkA) {
+    const float xs = ldexpf(m[q], e);
+    const uint16_t h = Conv16<T16>::to(xs);
+    hi[q] = h;
+    lo[q] = Conv16<T16>::to(ldexpf(xs - Conv16<T16>::from(h), t));
+  }
+}
+
+hipError_t launch_resplit(dmpt_precision prec, const LayerState* fwd, int j, int layer,
+                          const void* master, void* hi, void* lo, int64_t elems, int t,
+                          hipStream_t s) {
+  if (prec == DMPT_SPLIT_FP16)
+    hipLaunchKernelGGL(k_resplit<_Float16>, dim3(4096), dim3(kBlkA), 0, s, fwd, j, layer,
+                       (const float*)master, (uint16_t*)hi, (uint16_t*)lo, elems, t);
+  else if (prec == DMPT_SPLIT_BF16)
+    hipLaunchKernelGGL(k_resplit<__bf16>, dim3(4096), dim3(kBlkA), 0, s, fwd, j, layer,
+                       (const float*)master, (uint16_t*)hi, (uint16_t*)lo, elems, t);
+  return hipGetLastError();
+}
+
+// Sh1 seed: (W + W^T)/2 into the padded workspace layout (zero elsewhere).
+template <typename M>
+__global__ void __launch_bounds__(kBlkA) k_adj_seed(const double* W, int64_t n, int64_t rows,
+                                                   int64_t ld, M* dst) {
+  const int64_t total = rows * ld;
+  for (int64_t q = (int64_t)blockIdx.x * kBlkA + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * kBlkA) {
+    const int64_t i = q / ld, j = q - i * ld;
+    double v = 0.0;
+    if (i < n && j < n) v = 0.5 * (W[i * n + j] + W[j * n + i]);
+    dst[q] = (M)v;
+  }
+}
+
+hipError_t launch_adj_seed(dmpt_precision prec, const double* W, int64_t n, int64_t rows,
+                           int64_t ld, void* dst, hipStream_t s) {
+  if (prec == DMPT_FP64)
+    hipLaunchKernelGGL(k_adj_seed<double>, dim3(4096), dim3(kBlkA), 0, s, W, n, rows, ld,
+                       (double*)dst);
+  else
+    hipLaunchKernelGGL(k_adj_seed<float>, dim3(4096), dim3(kBlkA), 0, s, W, n, rows, ld,
+                       (float*)dst);
+  return hipGetLastError();
+}
+
+// One reverse layer: T2 = S Sh + Sh S, T1_k = S Sh1_k + Sh1_k S and
+// T3_k = Sh1_k S1_k + S1_k Sh1_k were formed by the product kernel from the
+// adjoints of layer n; this writes the adjoints of layer n - 1 in place.
+struct AdjPtrs {
+  const void* t1[kMaxK];
+  void* sh1[kMaxK];
+  const void* t3[kMaxK];
+};
+
+template <typename M>
+__global__ void __launch_bounds__(kBlkA) k_adj_update(const LayerState* f, int n, int k,
+                                                     const M* t2, M* sh, AdjPtrs p,
+                                                     int64_t elems) {
+  const M sig = (M)f->sigma[n];
+  const int d0l = f->d0_layer > 0 ? f->d0_layer : (1 << 30);
+  const bool s_upd = n < d0l;
+  bool upd[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) {
+    const int d1l = (j < k && f->d1_layer[j] > 0) ? f->d1_layer[j] : (1 << 30);
+    upd[j] = j < k && n < d1l;
+  }
+  for (int64_t q = (int64_t)blockIdx.x * kBlkA + threadIdx.x; q < elems;
+       q += (int64_t)gridDim.x * kBlkA) {
+    M v = sh[q];
+    if (s_upd) v = sig * t2[q] + ((M)1 - sig) * v;
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+      if (!upd[j]) continue;
+      const M* t1 = (const M*)p.t1[j];
+      const M* t3 = (const M*)p.t3[j];
+      M* s1 = (M*)p.sh1[j];
+      v += sig * t3[q];
+      s1[q] = sig * t1[q] + ((M)1 - sig) * s1[q];
+    }
+    sh[q] = v;
+  }
+}
+
+hipError_t launch_adj_update(dmpt_precision prec, const LayerState* fwd, int layer, int k,
+                             const void* t2, void* sh, const void* const* t1, void* const* sh1,
+                             const void* const* t3, int64_t elems, hipStream_t s) {
+  AdjPtrs p;
+  for (int j = 0; j < kMaxK; ++j) {
+    p.t1[j] = j < k ? t1[j] : nullptr;
+    p.sh1[j] = j < k ? sh1[j] : nullptr;
+    p.t3[j] = j < k ? t3[j] : nullptr;
+  }
+  if (prec == DMPT_FP64)
+    hipLaunchKernelGGL(k_adj_update<double>, dim3(4096), dim3(kBlkA), 0, s, fwd, layer, k,
+                       (const double*)t2, (double*)sh, p, elems);
+  else
+    hipLaunchKernelGGL(k_adj_update<float>, dim3(4096), dim3(kBlkA), 0, s, fwd, layer, k,
+                       (const float*)t2, (float*)sh, p, elems);
+  return hipGetLastError();
+}
+
+// dL/dH = -Sh_0 / (eps_N - eps_1)  (FP64, N x N).
+template <typename M>
+__global__ void __launch_bounds__(kBlkA) k_adj_out(const LayerState* f, const M* src, int64_t ld,
+                                                  double* dst, int64_t n) {
+  const double scale = -1.0 / (f->epsN - f->eps1);
+  const int64_t total = n * n;
+  for (int64_t q = (int64_t)blockIdx.x * kBlkA + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * kBlkA) {
+    const int64_t i = q / n, j = q - i * n;
+    dst[q] = scale * (double)src[i * ld + j];
+  }
+}
+
+hipError_t launch_adj_out(dmpt_precision prec, const LayerState* fwd, const void* src, int64_t ld,
+                          double* dst, int64_t n, hipStream_t s) {
+  if (prec == DMPT_FP64)
+    hipLaunchKernelGGL(k_adj_out<double>, dim3(4096), dim3(kBlkA), 0, s, fwd, (const double*)src,
+                       ld, dst, n);
+  else
+    hipLaunchKernelGGL(k_adj_out<float>, dim3(4096), dim3(kBlkA), 0, s, fwd, (const float*)src, ld,
+                       dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace dmpt

@@ -15,6 +15,8 @@
 //   acc = (2^t hi_A) hi_B + hi_A lo_B + lo_A hi_B  ( = 2^(t + eA + eB) A B )
 // and the epilogue multiplies by 2^-(t + eA + eB).  The lo*lo term is dropped
 // as in the paper.  The 2^t factor is applied to hi_A in registers (exact).
+#include <stdlib.h>
+
 #include "dmpt_internal.h"
 
 namespace dmpt {
@@ -79,17 +81,31 @@ k_products_split(const ProductArgs a) {
   constexpr int CH = BK / 8;                 // 16-byte chunks per row of a k-tile
   constexpr int ROWS = 2 * BM + 2 * BN;      // A_hi | A_lo | B_hi | B_lo
   constexpr int STAGE = ROWS * CH;           // chunks per pipeline stage
-  constexpr int RPL = NT / CH;               // rows covered by one load round
+  constexpr int RPW = kWave / CH;            // rows one wave fills per load instruction
+  constexpr int RPL = NT / CH;               // rows all waves fill per load round
   constexpr int LOADS = ROWS / RPL;          // load rounds per k-tile
   static_assert(ROWS % RPL == 0 && BM % RPL == 0, "load rounds must not straddle arrays");
   static_assert(BK % 16 == 0 && WTM % 32 == 0 && WTN % 32 == 0, "tile shape");
   extern __shared__ u32x4 lds[];
 
-  const int item_id = xcd_remap(blockIdx.x, gridDim.x);
-  if (item_id >= a.n_items) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int wm = wave / WGN, wn = wave % WGN;
+  // Loads go straight from global memory into LDS (global_load_lds_dwordx4):
+  // lane l of a wave writes the 16-byte slot l of the wave's 1 KB destination,
+  // i.e. row lrow, slot lsl.  The slot is the XOR-swizzled position of chunk
+  // lsl ^ swz(row), so that lane fetches that chunk from global memory.
+  const int lrow = tid / CH, lsl = tid % CH;
+
+  // Persistent grid: round r hands item r * G + slot to this workgroup; the
+  // slots of one XCD are contiguous, so in every round the CUs of an XCD work
+  // on a compact block of tiles and step through k together.
+  const int slot = xcd_remap(blockIdx.x, gridDim.x);
+  for (int item_id = slot; item_id < a.n_items; item_id += gridDim.x) {
   const TileItem it = a.items[item_id];
   int sexp = 0;
-  if (!item_active(a, it, &sexp)) return;
+  if (!item_active(a, it, &sexp)) continue;
 
   const int64_t ld = a.ld;
   const int j = it.out - 1;
@@ -109,33 +125,28 @@ k_products_split(const ProductArgs a) {
       P[1][0] = th; P[1][1] = tl; P[1][2] = sh; P[1][3] = sl;
     }
   }
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
-  const int wm = wave / WGN, wn = wave % WGN;
-  const int lrow = tid / CH, lch = tid % CH;
   const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BN;
-  const int kt_per = (int)(ld / BK);
+  const int kt_per = (int)(a.kdim / BK);
   const int ktiles = nprod * kt_per;
 
-  u32x4 regs[LOADS];
-  auto gload = [&](int t) {
+  // Per-thread part of the source offsets; the swizzle of row i*RPL + lrow
+  // does not depend on i, so every load round adds only a wave-uniform offset.
+  static_assert((RPL >> SWZ) % CH == 0, "swizzle must repeat every load round");
+  const int csrc = lsl ^ ((lrow >> SWZ) & (CH - 1));
+  const int64_t voff_a = (row_a0 + lrow) * ld + csrc * 8;
+  const int64_t voff_b = (row_b0 + lrow) * ld + csrc * 8;
+  auto issue = [&](int t) {
     const int p = t / kt_per;
     const int64_t k0 = (int64_t)(t - p * kt_per) * BK;
+    u32x4* dst_stage = lds + (t & 1) * STAGE;
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int arr = (i * RPL) / BM;             // compile-time after unrolling
-      const int r = i * RPL - arr * BM + lrow;
-      const int64_t grow = (arr < 2 ? row_a0 : row_b0) + r;
-      const uint16_t* basep = p == 0 ? P[0][arr] : P[1][arr];
-      regs[i] = *(const u32x4*)(basep + grow * ld + k0 + lch * 8);
-    }
-  };
-  auto lstore = [&](int stage) {
-#pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
-      const int R = i * RPL + lrow;
-      lds[stage * STAGE + R * CH + (lch ^ ((R >> SWZ) & (CH - 1)))] = regs[i];
+      const int64_t soff = (int64_t)(i * RPL - arr * BM) * ld + k0;   // wave-uniform
+      const uint16_t* basep = (p == 0 ? P[0][arr] : P[1][arr]) + soff;
+      u32x4* dst = dst_stage + (i * RPL + wave * RPW) * CH;            // wave-uniform
+      __builtin_amdgcn_global_load_lds((const void*)(basep + (arr < 2 ? voff_a : voff_b)),
+                                       (void*)dst, 16, 0, 0);
     }
   };
 
@@ -147,13 +158,13 @@ k_products_split(const ProductArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.0f;
 
-  gload(0);
-  lstore(0);
+  issue(0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int t = 0; t < ktiles; ++t) {
-    const int cur = t & 1;
-    if (t + 1 < ktiles) gload(t + 1);
-    const u32x4* base = lds + cur * STAGE;
+    // the other stage was released by every wave at the previous barrier
+    if (t + 1 < ktiles) issue(t + 1);
+    const u32x4* base = lds + (t & 1) * STAGE;
 #pragma unroll
     for (int kk = 0; kk < BK / 16; ++kk) {
       const int c = kk * 2 + (lane >> 5);
@@ -187,7 +198,9 @@ k_products_split(const ProductArgs a) {
 #pragma unroll
         for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(al[m], bh[n], acc[m][n]);
     }
-    if (t + 1 < ktiles) lstore(cur ^ 1);
+    // own loads of the next stage landed, then everyone: next stage readable,
+    // this stage free for the load after next
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
@@ -220,6 +233,7 @@ k_products_split(const ProductArgs a) {
         }
       }
     }
+  }  // items
 }
 
 // ------------------------------------------------------------------ direct forms
@@ -264,24 +278,26 @@ k_products_direct(const ProductArgs a) {
   static_assert(CH % 4 == 0, "k-tile must hold a multiple of 4 chunks");
   extern __shared__ u32x4 lds[];
 
-  const int item_id = xcd_remap(blockIdx.x, gridDim.x);
-  if (item_id >= a.n_items) return;
+  const int slot = xcd_remap(blockIdx.x, gridDim.x);
+  for (int item_id = slot; item_id < a.n_items; item_id += gridDim.x) {
   const TileItem it = a.items[item_id];
   int sexp = 0;
-  if (!item_active(a, it, &sexp)) return;
+  if (!item_active(a, it, &sexp)) continue;
   (void)sexp;  // direct forms store S1 unscaled
 
   const int64_t ld = a.ld;
   const int j = it.out - 1;
   const int nprod = it.out == 0 ? 1 : 2;
+  // out 0: S S;  out 1 + j: A B + B A with A = a_op[j] (default S), B = s1_hi[j]
   const T* P[2][2];
   {
     const T* s = (const T*)a.s_hi;
     if (it.out == 0) {
       P[0][0] = s; P[0][1] = s; P[1][0] = s; P[1][1] = s;
     } else {
-      const T* s1 = (const T*)a.s1_hi[j];
-      P[0][0] = s; P[0][1] = s1; P[1][0] = s1; P[1][1] = s;
+      const T* aa = a.a_op[j] ? (const T*)a.a_op[j] : s;
+      const T* bb = (const T*)a.s1_hi[j];
+      P[0][0] = aa; P[0][1] = bb; P[1][0] = bb; P[1][1] = aa;
     }
   }
   const int tid = threadIdx.x;
@@ -290,7 +306,7 @@ k_products_direct(const ProductArgs a) {
   const int wm = wave / WGN, wn = wave % WGN;
   const int lrow = tid / CH, lch = tid % CH;
   const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BN;
-  const int kt_per = (int)(ld / BK);
+  const int kt_per = (int)(a.kdim / BK);
   const int ktiles = nprod * kt_per;
 
   u32x4 regs[LOADS];
@@ -377,6 +393,7 @@ k_products_direct(const ProductArgs a) {
         if (!diag || gr < gc) C[gc * ld + gr] = v;
       }
     }
+  }  // items
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -385,44 +402,77 @@ constexpr int kSplitBM = 256, kSplitBK = 32, kSplitWGM = 2, kSplitWGN = 4, kSpli
 constexpr int kDirBM = 128, kDirWGM = 2, kDirWGN = 2, kDirSWZ = 1;
 constexpr int kDirBK32 = 32, kDirBK64 = 16;
 
+// Wave layout of the split products (tuning knob DMPT_SPLIT_WAVES = 4 or 8).
+static int split_waves() {
+  static int w = 0;
+  if (w == 0) {
+    const char* e = getenv("DMPT_SPLIT_WAVES");
+    w = (e && atoi(e) == 4) ? 4 : 8;
+  }
+  return w;
+}
+
 int product_tile(dmpt_precision prec) {
   return (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16) ? kSplitBM : kDirBM;
 }
 
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
 template <typename K>
-static hipError_t launch_one(K kernel, int threads, size_t lds_bytes, const ProductArgs& a,
-                             hipStream_t s) {
+static hipError_t launch_one(K kernel, int threads, size_t lds_bytes, int wg_per_cu,
+                             const ProductArgs& a, hipStream_t s) {
   static_assert(sizeof(ProductArgs) < 4096, "kernel argument block");
   hipError_t e = hipFuncSetAttribute((const void*)kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
   if (a.n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kernel, dim3(a.n_items), dim3(threads), lds_bytes, s, a);
+  // as many workgroups as can be resident at once (LDS and registers decide)
+  const int cap = wg_per_cu * device_cus();
+  const int grid = a.n_items < cap ? a.n_items : cap;
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds_bytes, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s) {
-  if (a.ld % product_tile(prec) != 0) return hipErrorInvalidValue;
+  // tiles cover [0, kdim)^2 exactly; rows must keep 16-byte alignment
+  if (a.kdim % product_tile(prec) != 0 || a.ld < a.kdim || a.ld % 8 != 0)
+    return hipErrorInvalidValue;
   switch (prec) {
     case DMPT_SPLIT_FP16: {
       constexpr size_t lds = 2 * (4 * kSplitBM) * (kSplitBK / 8) * 16;
+      if (split_waves() == 4)
+        return launch_one(k_products_split<_Float16, kSplitBM, kSplitBK, 2, 2, kSplitSWZ>,
+                          4 * kWave, lds, 1, a, s);
       return launch_one(k_products_split<_Float16, kSplitBM, kSplitBK, kSplitWGM, kSplitWGN, kSplitSWZ>,
-                        kSplitWGM * kSplitWGN * kWave, lds, a, s);
+                        kSplitWGM * kSplitWGN * kWave, lds, 1, a, s);
     }
     case DMPT_SPLIT_BF16: {
       constexpr size_t lds = 2 * (4 * kSplitBM) * (kSplitBK / 8) * 16;
+      if (split_waves() == 4)
+        return launch_one(k_products_split<__bf16, kSplitBM, kSplitBK, 2, 2, kSplitSWZ>,
+                          4 * kWave, lds, 1, a, s);
       return launch_one(k_products_split<__bf16, kSplitBM, kSplitBK, kSplitWGM, kSplitWGN, kSplitSWZ>,
-                        kSplitWGM * kSplitWGN * kWave, lds, a, s);
+                        kSplitWGM * kSplitWGN * kWave, lds, 1, a, s);
     }
     case DMPT_FP32: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK32 / 4) * 16;
       return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN, kDirSWZ>,
-                        kDirWGM * kDirWGN * kWave, lds, a, s);
+                        kDirWGM * kDirWGN * kWave, lds, 2, a, s);
     }
     case DMPT_FP64: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK64 / 2) * 16;
       return launch_one(k_products_direct<double, kDirBM, kDirBK64, kDirWGM, kDirWGN, kDirSWZ>,
-                        kDirWGM * kDirWGN * kWave, lds, a, s);
+                        kDirWGM * kDirWGN * kWave, lds, 2, a, s);
     }
   }
   return hipErrorInvalidValue;

@@ -190,10 +190,10 @@ hipError_t launch_maxabs(const double* H, int64_t n, double* part, hipStream_t s
 // into a padded Np x Np matrix (padding is zero and stays zero: a zero
 // eigenvalue is a fixed point of both x^2 and 2x - x^2).
 template <typename M>
-__global__ void __launch_bounds__(kBlk) k_init_s0(const double* H0, int64_t n, int64_t ld,
-                                                 const LayerState* st, M* s_init) {
+__global__ void __launch_bounds__(kBlk) k_init_s0(const double* H0, int64_t n, int64_t rows,
+                                                 int64_t ld, const LayerState* st, M* s_init) {
   const double en = st->epsN, w = st->epsN - st->eps1;
-  const int64_t total = ld * ld;
+  const int64_t total = rows * ld;
   for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total;
        q += (int64_t)gridDim.x * kBlk) {
     const int64_t i = q / ld, j = q - i * ld;
@@ -203,12 +203,14 @@ __global__ void __launch_bounds__(kBlk) k_init_s0(const double* H0, int64_t n, i
   }
 }
 
-hipError_t launch_init_s0(dmpt_precision prec, const double* H0, int64_t n, int64_t ld,
-                          const LayerState* st, void* s_init, hipStream_t s) {
+hipError_t launch_init_s0(dmpt_precision prec, const double* H0, int64_t n, int64_t rows,
+                          int64_t ld, const LayerState* st, void* s_init, hipStream_t s) {
   if (prec == DMPT_FP64)
-    hipLaunchKernelGGL(k_init_s0<double>, dim3(4096), dim3(kBlk), 0, s, H0, n, ld, st, (double*)s_init);
+    hipLaunchKernelGGL(k_init_s0<double>, dim3(4096), dim3(kBlk), 0, s, H0, n, rows, ld, st,
+                       (double*)s_init);
   else
-    hipLaunchKernelGGL(k_init_s0<float>, dim3(4096), dim3(kBlk), 0, s, H0, n, ld, st, (float*)s_init);
+    hipLaunchKernelGGL(k_init_s0<float>, dim3(4096), dim3(kBlk), 0, s, H0, n, rows, ld, st,
+                       (float*)s_init);
   return hipGetLastError();
 }
 
@@ -225,8 +227,8 @@ __global__ void __launch_bounds__(kBlk) k_load(const M* src, M* master, uint16_t
 }
 
 hipError_t launch_load_s0(dmpt_precision prec, const void* s_init, void* master, void* hi, void* lo,
-                          int64_t ld, int t, hipStream_t s) {
-  const int64_t total = ld * ld;
+                          int64_t rows, int64_t ld, int t, hipStream_t s) {
+  const int64_t total = rows * ld;
   switch (prec) {
     case DMPT_FP64:
       hipLaunchKernelGGL((k_load<double, _Float16, false>), dim3(4096), dim3(kBlk), 0, s,
@@ -264,19 +266,20 @@ __global__ void __launch_bounds__(kBlk) k_s1_setup(const double* part, int nb, L
     const int e = split_exponent(mx);
     st->s1_exp_split[j] = e;
     st->s1_exp_next[j] = e;
+    st->s1_exp_hist[j][0] = e;
     st->s1_max[j] = mx;
   }
 }
 
 // Step 2: S1_0 (padded) in the layer precision, split with the state's scale.
 template <typename M, typename T16, bool SPLIT>
-__global__ void __launch_bounds__(kBlk) k_init_s1(const double* H1, int64_t n, int64_t ld,
-                                                 const LayerState* st, int j, double w_fixed,
-                                                 int use_state_eps, M* s1, uint16_t* hi,
-                                                 uint16_t* lo, int t) {
+__global__ void __launch_bounds__(kBlk) k_init_s1(const double* H1, int64_t n, int64_t rows,
+                                                 int64_t ld, const LayerState* st, int j,
+                                                 double w_fixed, int use_state_eps, M* s1,
+                                                 uint16_t* hi, uint16_t* lo, int t) {
   const double w = use_state_eps ? st->epsN - st->eps1 : w_fixed;
   const int e = st->s1_exp_split[j];
-  const int64_t total = ld * ld;
+  const int64_t total = rows * ld;
   for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total;
        q += (int64_t)gridDim.x * kBlk) {
     const int64_t r = q / ld, c = q - r * ld;
@@ -288,9 +291,9 @@ __global__ void __launch_bounds__(kBlk) k_init_s1(const double* H1, int64_t n, i
   }
 }
 
-hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int64_t ld,
-                          LayerState* st, int j, double* part, void* s1, void* hi, void* lo, int t,
-                          double w_fixed, hipStream_t s) {
+hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int64_t rows,
+                          int64_t ld, LayerState* st, int j, double* part, void* s1, void* hi,
+                          void* lo, int t, double w_fixed, hipStream_t s) {
   const int use_state = w_fixed > 0.0 ? 0 : 1;
   hipLaunchKernelGGL(k_maxabs, dim3(kRedBlocks), dim3(kBlk), 0, s, H1, n * n, part);
   hipLaunchKernelGGL(k_s1_setup, dim3(1), dim3(kBlk), 0, s, part, kRedBlocks, st, j, use_state,
@@ -298,18 +301,18 @@ hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int6
   switch (prec) {
     case DMPT_FP64:
       hipLaunchKernelGGL((k_init_s1<double, _Float16, false>), dim3(4096), dim3(kBlk), 0, s, H1, n,
-                         ld, st, j, w_fixed, use_state, (double*)s1, nullptr, nullptr, t);
+                         rows, ld, st, j, w_fixed, use_state, (double*)s1, nullptr, nullptr, t);
       break;
     case DMPT_FP32:
       hipLaunchKernelGGL((k_init_s1<float, _Float16, false>), dim3(4096), dim3(kBlk), 0, s, H1, n,
-                         ld, st, j, w_fixed, use_state, (float*)s1, nullptr, nullptr, t);
+                         rows, ld, st, j, w_fixed, use_state, (float*)s1, nullptr, nullptr, t);
       break;
     case DMPT_SPLIT_FP16:
       hipLaunchKernelGGL((k_init_s1<float, _Float16, true>), dim3(4096), dim3(kBlk), 0, s, H1, n,
-                         ld, st, j, w_fixed, use_state, (float*)s1, (uint16_t*)hi, (uint16_t*)lo, t);
+                         rows, ld, st, j, w_fixed, use_state, (float*)s1, (uint16_t*)hi, (uint16_t*)lo, t);
       break;
     case DMPT_SPLIT_BF16:
-      hipLaunchKernelGGL((k_init_s1<float, __bf16, true>), dim3(4096), dim3(kBlk), 0, s, H1, n, ld,
+      hipLaunchKernelGGL((k_init_s1<float, __bf16, true>), dim3(4096), dim3(kBlk), 0, s, H1, n, rows, ld,
                          st, j, w_fixed, use_state, (float*)s1, (uint16_t*)hi, (uint16_t*)lo, t);
       break;
   }
@@ -481,9 +484,9 @@ __global__ void __launch_bounds__(kBlk) k_update(const LayerState* st, int which
 }
 
 hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, const void* x,
-                         const void* s_old, void* dst, void* hi, void* lo, int64_t ld, int t,
+                         const void* s_old, void* dst, void* hi, void* lo, int64_t elems, int t,
                          double* pfro, double* pmax, hipStream_t s) {
-  const int64_t total = ld * ld;
+  const int64_t total = elems;
   switch (prec) {
     case DMPT_FP64:
       hipLaunchKernelGGL((k_update<double, _Float16, false>), dim3(kRedBlocks), dim3(kBlk), 0, s, st,
@@ -567,6 +570,7 @@ __global__ void __launch_bounds__(kBlk) k_decide1(LayerState* st, const double* 
         }
       }
     }
+    st->s1_exp_hist[j][n] = st->s1_exp_next[j];   // the scale S1_n was just split with
     st->s1_exp_split[j] = st->s1_exp_next[j];
     st->s1_exp_next[j] = split_exponent(mx);
     st->s1_max[j] = mx;
@@ -632,9 +636,10 @@ hipError_t launch_trace(const double* P, int64_t n, double* out, hipStream_t s) 
 
 // A (FP64 N x N) -> padded layer-precision master (+ split with scale 2^e).
 template <typename M, typename T16, bool SPLIT>
-__global__ void __launch_bounds__(kBlk) k_from_f64(const double* A, int64_t n, int64_t ld, int e,
-                                                  int t, M* master, uint16_t* hi, uint16_t* lo) {
-  const int64_t total = ld * ld;
+__global__ void __launch_bounds__(kBlk) k_from_f64(const double* A, int64_t n, int64_t rows,
+                                                  int64_t ld, int e, int t, M* master,
+                                                  uint16_t* hi, uint16_t* lo) {
+  const int64_t total = rows * ld;
   for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total;
        q += (int64_t)gridDim.x * kBlk) {
     const int64_t i = q / ld, j = q - i * ld;
@@ -644,23 +649,24 @@ __global__ void __launch_bounds__(kBlk) k_from_f64(const double* A, int64_t n, i
   }
 }
 
-hipError_t launch_from_f64(dmpt_precision prec, const double* A, int64_t n, int64_t ld, int e,
-                           int t, void* master, void* hi, void* lo, hipStream_t s) {
+hipError_t launch_from_f64(dmpt_precision prec, const double* A, int64_t n, int64_t rows,
+                           int64_t ld, int e, int t, void* master, void* hi, void* lo,
+                           hipStream_t s) {
   switch (prec) {
     case DMPT_FP64:
       hipLaunchKernelGGL((k_from_f64<double, _Float16, false>), dim3(4096), dim3(kBlk), 0, s, A, n,
-                         ld, e, t, (double*)master, nullptr, nullptr);
+                         rows, ld, e, t, (double*)master, nullptr, nullptr);
       break;
     case DMPT_FP32:
       hipLaunchKernelGGL((k_from_f64<float, _Float16, false>), dim3(4096), dim3(kBlk), 0, s, A, n,
-                         ld, e, t, (float*)master, nullptr, nullptr);
+                         rows, ld, e, t, (float*)master, nullptr, nullptr);
       break;
     case DMPT_SPLIT_FP16:
       hipLaunchKernelGGL((k_from_f64<float, _Float16, true>), dim3(4096), dim3(kBlk), 0, s, A, n,
-                         ld, e, t, (float*)master, (uint16_t*)hi, (uint16_t*)lo);
+                         rows, ld, e, t, (float*)master, (uint16_t*)hi, (uint16_t*)lo);
       break;
     case DMPT_SPLIT_BF16:
-      hipLaunchKernelGGL((k_from_f64<float, __bf16, true>), dim3(4096), dim3(kBlk), 0, s, A, n, ld,
+      hipLaunchKernelGGL((k_from_f64<float, __bf16, true>), dim3(4096), dim3(kBlk), 0, s, A, n, rows, ld,
                          e, t, (float*)master, (uint16_t*)hi, (uint16_t*)lo);
       break;
   }

@@ -1,0 +1,132 @@
+"""Parity of the hand-written adjoint (dmpt_adjoint) with the oracle's
+closed-form gradients of L = Tr(P1 W), and with central finite differences of
+the FP64 GPU forward on sampled entries."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_2203_09621_amd as dm
+    return dm
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _grads(dm, p, precision, ckpt):
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=1, precision=precision, ckpt_every=ckpt)
+    try:
+        _, (P1,), st = dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+        g0, (g1,), ast = dm.dmpt_adjoint(ctx, [_cuda(p.W)])
+    finally:
+        dm.dmpt_destroy(ctx)
+    return P1.cpu().numpy(), g0.cpu().numpy(), g1.cpu().numpy(), st, ast
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def c5_small():
+    from workloads import config5
+    return config5(n=384)
+
+
+@pytest.mark.parametrize("precision,tol", [("split_bf16", TOL), ("split_fp16", TOL),
+                                           ("fp32", TOL), ("fp64", 1e-8)])
+def test_adjoint_matches_closed_form(dm, c5_small, precision, tol):
+    from oracle import adjoint
+    p = c5_small
+    _, g0, g1, st, ast = _grads(dm, p, precision, 8)
+    r1 = adjoint.grad_h1(p.H0, [p.W], p.nocc)[0]
+    r0 = adjoint.grad_h0(p.H0, p.H1, [p.W], p.nocc)
+    e0, e1 = _rel(g0, r0), _rel(g1, r1)
+    print(f"adjoint {precision}: layers={st['layers']} dH0 err={e0:.2e} dH1 err={e1:.2e} "
+          f"({ast['ms']:.1f} ms)", flush=True)
+    assert e1 < tol and e0 < tol
+    assert np.array_equal(g0, g0.T) and np.array_equal(g1, g1.T)
+
+
+def test_checkpoint_interval_does_not_change_result(dm, c5_small):
+    """Recomputation replays the forward bitwise, so the interval is invisible."""
+    a = _grads(dm, c5_small, "split_bf16", 3)
+    b = _grads(dm, c5_small, "split_bf16", 8)
+    c = _grads(dm, c5_small, "split_bf16", 1)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert np.array_equal(a[1], c[1]) and np.array_equal(a[2], c[2])
+
+
+def test_adjoint_vs_fd_of_fp64_forward(dm, c5_small):
+    """Central differences (h = 1e-5) of L = <P1, W> from the FP64 GPU forward."""
+    p = c5_small
+    _, g0, g1, _, _ = _grads(dm, p, "fp64", 8)
+    rng = np.random.default_rng(17)
+    h = 1e-5
+
+    def lval(h0, h1):
+        _, (P1,), _ = dm.solve(_cuda(h0), [_cuda(h1)], p.nocc, precision="fp64")
+        return float(np.sum(P1.cpu().numpy() * p.W))
+
+    for _ in range(4):
+        i, j = sorted(int(x) for x in rng.integers(0, p.N, 2))
+        e = np.zeros((p.N, p.N))
+        e[i, j] = e[j, i] = 1.0
+        fac = 1.0 if i == j else 2.0
+        fd0 = (lval(p.H0 + h * e, p.H1[0]) - lval(p.H0 - h * e, p.H1[0])) / (2 * h) / fac
+        fd1 = (lval(p.H0, p.H1[0] + h * e) - lval(p.H0, p.H1[0] - h * e)) / (2 * h) / fac
+        scale0, scale1 = np.abs(g0).max(), np.abs(g1).max()
+        assert abs(fd0 - g0[i, j]) <= TOL * scale0, (i, j, fd0, g0[i, j])
+        assert abs(fd1 - g1[i, j]) <= TOL * scale1, (i, j, fd1, g1[i, j])
+
+
+def test_autograd_function(dm, c5_small):
+    import torch
+    from oracle import adjoint
+    p = c5_small
+    F = dm.response_function()
+    h0 = _cuda(p.H0).requires_grad_(True)
+    h1 = _cuda(p.H1[0]).requires_grad_(True)
+    P1 = F.apply(h0, h1, p.nocc, "split_bf16", 8)
+    loss = (P1 * _cuda(p.W)).sum()
+    loss.backward()
+    r1 = adjoint.grad_h1(p.H0, [p.W], p.nocc)[0]
+    r0 = adjoint.grad_h0(p.H0, p.H1, [p.W], p.nocc)
+    assert _rel(h1.grad.cpu().numpy(), r1) < TOL
+    assert _rel(h0.grad.cpu().numpy(), r0) < TOL
+    del torch
+
+
+def test_adjoint_requires_checkpoints(dm, c5_small):
+    p = c5_small
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=1, precision="split_bf16")
+    try:
+        dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+        with pytest.raises(dm.DmptError) as ei:
+            dm.dmpt_adjoint(ctx, [_cuda(p.W)])
+        assert ei.value.status == -1
+    finally:
+        dm.dmpt_destroy(ctx)
+
+
+def test_adjoint_full_size(dm):
+    """N = 4096, gap 0.5, split-BF16 forward, FP32 adjoint, checkpoint every 8."""
+    from oracle import adjoint
+    from workloads import config5
+    p = config5()
+    _, g0, g1, st, ast = _grads(dm, p, "split_bf16", 8)
+    r1 = adjoint.grad_h1(p.H0, [p.W], p.nocc)[0]
+    r0 = adjoint.grad_h0(p.H0, p.H1, [p.W], p.nocc)
+    e0, e1 = _rel(g0, r0), _rel(g1, r1)
+    print(f"adjoint N=4096: layers={st['layers']} dH0 err={e0:.2e} dH1 err={e1:.2e} "
+          f"forward {st['ms']:.1f} ms adjoint {ast['ms']:.1f} ms", flush=True)
+    assert e0 < TOL and e1 < TOL

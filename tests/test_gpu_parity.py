@@ -165,3 +165,15 @@ def test_diagonal_h0_terminates(dm):
     P0, P1s, st = dm.solve(_cuda(np.diag(e)), [_cuda(h1)], 60, precision="fp64")
     assert st["converged"]
     assert exact.rel_fro(P1s[0].cpu().numpy(), exact.density_response(np.diag(e), h1, 60)) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "fp64"])
+def test_padded_row_stride(dm, precision, monkeypatch):
+    """Workspace rows longer than Np (pad columns must stay zero)."""
+    from workloads import config2
+    monkeypatch.setenv("DMPT_LD_PAD", "72")
+    p = config2(n=520)
+    P0, P1s, st = _solve(dm, p, precision)
+    e0, e1 = _errors(p, P0, P1s)
+    tol = FP64_TOL if precision == "fp64" else SPLIT_TOL
+    assert st["converged"] and e0 < tol and max(e1) < tol

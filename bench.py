@@ -65,6 +65,28 @@ def k_active(stats):
     return [sum(1 for e in ends if layer <= e) for layer in range(1, L + 1)]
 
 
+def measured_traffic(workload, precision):
+    """HBM bytes per product launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration), or None
+    when no summary covers this workload or the product kernel source changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    if workload != "c3" or not precision.startswith("split"):
+        return None
+    path = os.path.join(ROOT, "profiles", "k_products_split_N16384_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2203_09621_amd", "csrc", "kernels_gemm.hip")
+    try:
+        m = re.search(r"```json\n(.*?)```", open(path).read(), re.S)
+        data = json.loads(m.group(1))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except Exception:
+        return None
+    if data.get("source_sha256_16") != cur:
+        return None
+    return data["fetch_bytes_per_launch"] + data["write_bytes_per_launch"]
+
+
 def oracle_errors(p, P0, P1s):
     from oracle import exact
     t = time.perf_counter()
@@ -177,7 +199,10 @@ def main():
                    "d1_layer": st["d1_layer"]},
         "time_to_p1_ms": round(ms, 3),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic(args.workload, args.precision),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-kernel calibrated)",
                      "kernel": "k_products_split" if args.precision.startswith("split")
                      else "k_products_direct",
                      "avg_launch_ms": round(prod_ms / max(launches, 1), 4),

@@ -267,16 +267,17 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
   get(&c->s_init, mat * eb);
   get(&c->s_master, mat * eb);
   get(&c->x, mat * eb);
+  const size_t pmat = (size_t)c->np * c->np;   // panel-major 16-bit operands
   if (is_split(c->prec)) {
-    get(&c->s_hi, mat * 2);
-    get(&c->s_lo, mat * 2);
+    get(&c->s_hi, pmat * 2);
+    get(&c->s_lo, pmat * 2);
   }
   for (int j = 0; j < k_max; ++j) {
     get(&c->s1buf[j][0], mat * eb);
     get(&c->s1buf[j][1], mat * eb);
     if (is_split(c->prec)) {
-      get(&c->s1_hi[j], mat * 2);
-      get(&c->s1_lo[j], mat * 2);
+      get(&c->s1_hi[j], pmat * 2);
+      get(&c->s1_lo[j], pmat * 2);
     }
   }
   get((void**)&c->part, kPartTotal * sizeof(double));
@@ -426,11 +427,11 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
     HIPCHK(launch_products(prec, pa, s));
     if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1) + 1], s));
     HIPCHK(launch_decide0(prec, c->st, c->x, ld, s));
-    HIPCHK(launch_update(prec, c->st, -1, c->x, c->s_master, c->s_master, c->s_hi, c->s_lo, elems,
-                         t, c->part + kPartFro0, nullptr, s));
+    HIPCHK(launch_update(prec, c->st, -1, c->x, c->s_master, c->s_master, c->s_hi, c->s_lo, np,
+                         ld, t, c->part + kPartFro0, nullptr, s));
     for (int j = 0; j < k; ++j)
       HIPCHK(launch_update(prec, c->st, j, c->s1buf[j][cur], c->s1buf[j][prv], c->s1buf[j][cur],
-                           c->s1_hi[j], c->s1_lo[j], elems, t,
+                           c->s1_hi[j], c->s1_lo[j], np, ld, t,
                            c->part + kPartFro1 + (size_t)j * kRedBlocks,
                            c->part + kPartMax1 + (size_t)j * kRedBlocks, s));
     HIPCHK(launch_decide1(c->st, c->part + kPartFro0, c->part + kPartFro1, c->part + kPartMax1,
@@ -546,12 +547,13 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
                             hipMemcpyDeviceToDevice, s));
     if (e - 1 >= b + 1) {
       HIPCHK(hipMemcpyAsync(c->s_master, c->seg_s[0], mbytes, hipMemcpyDeviceToDevice, s));
-      if (split) HIPCHK(launch_resplit(prec, c->st, -1, 0, c->s_master, c->s_hi, c->s_lo, elems, t, s));
+      if (split)
+        HIPCHK(launch_resplit(prec, c->st, -1, 0, c->s_master, c->s_hi, c->s_lo, np, ld, t, s));
       for (int j = 0; j < k; ++j) {
         HIPCHK(hipMemcpyAsync(c->s1buf[j][b & 1], c->seg_s1[j], mbytes, hipMemcpyDeviceToDevice, s));
         if (split)
           HIPCHK(launch_resplit(prec, c->st, j, b, c->s1buf[j][b & 1], c->s1_hi[j], c->s1_lo[j],
-                                elems, t, s));
+                                np, ld, t, s));
       }
       for (int n = b + 1; n <= e - 1; ++n) {
         const int cur = n & 1, prv = cur ^ 1;
@@ -563,10 +565,10 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
         }
         HIPCHK(launch_products(prec, fa, s));
         HIPCHK(launch_update(prec, c->st_rep, -1, c->x, c->s_master, c->s_master, c->s_hi, c->s_lo,
-                             elems, t, c->part + kPartFro0, nullptr, s));
+                             np, ld, t, c->part + kPartFro0, nullptr, s));
         for (int j = 0; j < k; ++j)
           HIPCHK(launch_update(prec, c->st_rep, j, c->s1buf[j][cur], c->s1buf[j][prv],
-                               c->s1buf[j][cur], c->s1_hi[j], c->s1_lo[j], elems, t,
+                               c->s1buf[j][cur], c->s1_hi[j], c->s1_lo[j], np, ld, t,
                                c->part + kPartFro1 + (size_t)j * kRedBlocks,
                                c->part + kPartMax1 + (size_t)j * kRedBlocks, s));
         HIPCHK(hipMemcpyAsync(c->seg_s[n - b], c->s_master, mbytes, hipMemcpyDeviceToDevice, s));
@@ -634,18 +636,19 @@ dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, c
   auto get = [&](void** p, size_t b) {
     if (e == hipSuccess) e = mem.get(p, b);
   };
+  const size_t pmat = (size_t)np * np;   // panel-major 16-bit operands
   get(&sm, mat * eb);
   get(&xo, mat * eb);
   if (split) {
-    get(&sh, mat * 2);
-    get(&sl, mat * 2);
+    get(&sh, pmat * 2);
+    get(&sl, pmat * 2);
   }
   if (S1) {
     get(&tm, mat * eb);
     get(&x1o, mat * eb);
     if (split) {
-      get(&th, mat * 2);
-      get(&tl, mat * 2);
+      get(&th, pmat * 2);
+      get(&tl, pmat * 2);
     }
   }
   get((void**)&part, kRedBlocks * sizeof(double));

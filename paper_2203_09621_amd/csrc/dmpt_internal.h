@@ -27,6 +27,17 @@ constexpr int kRedBlocks = 1024;  // fixed grid of the reducing elementwise kern
 constexpr int kLoShiftF16 = 11;
 constexpr int kLoShiftBF16 = 0;
 
+// Panel-major layout of the 16-bit split operands: the Np x Np matrix is cut
+// into blocks of kPanelRows rows x kPanelK columns, each block stored
+// contiguously (row-major inside), the blocks of one row panel consecutive
+// along k.  A k-tile of a 256-row panel is then one contiguous 16 KB chunk.
+constexpr int kPanelRows = 256;
+constexpr int kPanelK = 32;
+__host__ __device__ __forceinline__ int64_t panel_index(int64_t r, int64_t c, int64_t kdim) {
+  return ((r / kPanelRows) * (kdim / kPanelK) + c / kPanelK) * (kPanelRows * kPanelK) +
+         (r % kPanelRows) * kPanelK + (c % kPanelK);
+}
+
 // ----------------------------------------------------------------- layer state
 // Scalar state of Algorithms 1-3 kept in device memory so that the layer loop
 // needs no host round trip.  Written only by the single-workgroup decision
@@ -116,8 +127,8 @@ hipError_t launch_reset_state(LayerState* st, int k, int max_layers, double nocc
 hipError_t launch_decide0(dmpt_precision prec, LayerState* st, const void* x, int64_t ld,
                           hipStream_t s);
 hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, const void* x,
-                         const void* s_old, void* dst, void* hi, void* lo, int64_t elems, int t,
-                         double* pfro, double* pmax, hipStream_t s);
+                         const void* s_old, void* dst, void* hi, void* lo, int64_t rows,
+                         int64_t ld, int t, double* pfro, double* pmax, hipStream_t s);
 hipError_t launch_decide1(LayerState* st, const double* pfro0, const double* pfro1,
                           const double* pmax1, int split, int lo_shift, hipStream_t s);
 hipError_t launch_copy_out(dmpt_precision prec, const LayerState* st, int which, const void* b0,
@@ -132,7 +143,7 @@ hipError_t launch_copy_plain(dmpt_precision prec, const void* src, int64_t ld, d
 // adjoint of the layer recursion (kernels_adjoint.hip)
 hipError_t launch_replay_state(const LayerState* fwd, LayerState* rep, int n, hipStream_t s);
 hipError_t launch_resplit(dmpt_precision prec, const LayerState* fwd, int j, int layer,
-                          const void* master, void* hi, void* lo, int64_t elems, int t,
+                          const void* master, void* hi, void* lo, int64_t rows, int64_t ld, int t,
                           hipStream_t s);
 hipError_t launch_adj_seed(dmpt_precision prec, const double* W, int64_t n, int64_t rows,
                            int64_t ld, void* dst, hipStream_t s);

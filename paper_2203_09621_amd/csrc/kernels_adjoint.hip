@@ -61,26 +61,30 @@ hipError_t launch_replay_state(const LayerState* fwd, LayerState* rep, int n, hi
 template <typename T16>
 __global__ void __launch_bounds__(kBlkA) k_resplit(const LayerState* f, int j, int layer,
                                                   const float* m, uint16_t* hi, uint16_t* lo,
-                                                  int64_t elems, int t) {
+                                                  int64_t rows, int64_t ld, int t) {
   const int e = j >= 0 ? f->s1_exp_hist[j][layer] : 0;
+  const int64_t elems = rows * ld;
   for (int64_t q = (int64_t)blockIdx.x * kBlkA + threadIdx.x; q < elems;
        q += (int64_t)gridDim.x * kBlkA) {
+    const int64_t r = q / ld, c = q - r * ld;
+    if (c >= rows) continue;
+    const int64_t pi = panel_index(r, c, rows);
     const float xs = ldexpf(m[q], e);
     const uint16_t h = Conv16<T16>::to(xs);
-    hi[q] = h;
-    lo[q] = Conv16<T16>::to(ldexpf(xs - Conv16<T16>::from(h), t));
+    hi[pi] = h;
+    lo[pi] = Conv16<T16>::to(ldexpf(xs - Conv16<T16>::from(h), t));
   }
 }
 
 hipError_t launch_resplit(dmpt_precision prec, const LayerState* fwd, int j, int layer,
-                          const void* master, void* hi, void* lo, int64_t elems, int t,
+                          const void* master, void* hi, void* lo, int64_t rows, int64_t ld, int t,
                           hipStream_t s) {
   if (prec == DMPT_SPLIT_FP16)
     hipLaunchKernelGGL(k_resplit<_Float16>, dim3(4096), dim3(kBlkA), 0, s, fwd, j, layer,
-                       (const float*)master, (uint16_t*)hi, (uint16_t*)lo, elems, t);
+                       (const float*)master, (uint16_t*)hi, (uint16_t*)lo, rows, ld, t);
   else if (prec == DMPT_SPLIT_BF16)
     hipLaunchKernelGGL(k_resplit<__bf16>, dim3(4096), dim3(kBlkA), 0, s, fwd, j, layer,
-                       (const float*)master, (uint16_t*)hi, (uint16_t*)lo, elems, t);
+                       (const float*)master, (uint16_t*)hi, (uint16_t*)lo, rows, ld, t);
   return hipGetLastError();
 }
 

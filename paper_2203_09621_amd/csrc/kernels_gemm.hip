@@ -69,7 +69,15 @@ __device__ __forceinline__ bool item_active(const ProductArgs& a, const TileItem
   return true;
 }
 
-template <typename T16, int BM, int BK, int WGM, int WGN, int SWZ>
+// s_waitcnt immediate that waits until at most N vector-memory operations are
+// outstanding and leaves the other counters unconstrained (gfx9 encoding).
+template <int N>
+struct VmWait {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  static constexpr int imm = (N & 15) | (((N >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
+};
+
+template <typename T16, int BM, int BK, int WGM, int WGN, int SWZ, int STAGES>
 __global__ void __launch_bounds__(WGM * WGN * kWave)
 k_products_split(const ProductArgs a) {
   using S = Split16<T16>;
@@ -129,24 +137,28 @@ k_products_split(const ProductArgs a) {
   const int kt_per = (int)(a.kdim / BK);
   const int ktiles = nprod * kt_per;
 
-  // Per-thread part of the source offsets; the swizzle of row i*RPL + lrow
-  // does not depend on i, so every load round adds only a wave-uniform offset.
+  // Operands are panel-major: the k-tile kt of row tile I is the contiguous
+  // block (I * kblocks + kt) of kPanelRows x kPanelK elements.  Per-thread
+  // offset inside a block; the swizzle of row i*RPL + lrow does not depend on
+  // i, so every load round adds only a wave-uniform offset.
+  static_assert(BM == kPanelRows && BK == kPanelK, "tile = panel block");
   static_assert((RPL >> SWZ) % CH == 0, "swizzle must repeat every load round");
+  const int64_t kblocks = a.kdim / kPanelK;
   const int csrc = lsl ^ ((lrow >> SWZ) & (CH - 1));
-  const int64_t voff_a = (row_a0 + lrow) * ld + csrc * 8;
-  const int64_t voff_b = (row_b0 + lrow) * ld + csrc * 8;
+  const int voff = lrow * kPanelK + csrc * 8;
   auto issue = [&](int t) {
     const int p = t / kt_per;
-    const int64_t k0 = (int64_t)(t - p * kt_per) * BK;
-    u32x4* dst_stage = lds + (t & 1) * STAGE;
+    const int64_t kt = t - p * kt_per;
+    u32x4* dst_stage = lds + (t % STAGES) * STAGE;
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int arr = (i * RPL) / BM;             // compile-time after unrolling
-      const int64_t soff = (int64_t)(i * RPL - arr * BM) * ld + k0;   // wave-uniform
+      const int64_t tile = arr < 2 ? it.ti : it.tj;
+      const int64_t soff = (tile * kblocks + kt) * (kPanelRows * kPanelK) +
+                           (int64_t)(i * RPL - arr * BM) * kPanelK;   // wave-uniform
       const uint16_t* basep = (p == 0 ? P[0][arr] : P[1][arr]) + soff;
       u32x4* dst = dst_stage + (i * RPL + wave * RPW) * CH;            // wave-uniform
-      __builtin_amdgcn_global_load_lds((const void*)(basep + (arr < 2 ? voff_a : voff_b)),
-                                       (void*)dst, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(basep + voff), (void*)dst, 16, 0, 0);
     }
   };
 
@@ -158,13 +170,21 @@ k_products_split(const ProductArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.0f;
 
-  issue(0);
-  __builtin_amdgcn_s_waitcnt(0);
+  // Prologue: tiles 0 .. STAGES-2 in flight, wait for tile 0 (and for the
+  // previous item's stores, which share the counter).
+#pragma unroll
+  for (int q = 0; q < STAGES - 1; ++q)
+    if (q < ktiles) issue(q);
+  if (ktiles >= STAGES - 1)
+    __builtin_amdgcn_s_waitcnt(VmWait<(STAGES - 2) * LOADS>::imm);
+  else
+    __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int t = 0; t < ktiles; ++t) {
-    // the other stage was released by every wave at the previous barrier
-    if (t + 1 < ktiles) issue(t + 1);
-    const u32x4* base = lds + (t & 1) * STAGE;
+    // stage (t-1) % STAGES was released by every wave at the previous barrier
+    const bool more = t + STAGES - 1 < ktiles;
+    if (more) issue(t + STAGES - 1);
+    const u32x4* base = lds + (t % STAGES) * STAGE;
 #pragma unroll
     for (int kk = 0; kk < BK / 16; ++kk) {
       const int c = kk * 2 + (lane >> 5);
@@ -198,9 +218,12 @@ k_products_split(const ProductArgs a) {
 #pragma unroll
         for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(al[m], bh[n], acc[m][n]);
     }
-    // own loads of the next stage landed, then everyone: next stage readable,
-    // this stage free for the load after next
-    __builtin_amdgcn_s_waitcnt(0);
+    // own loads of tile t+1 landed (tiles t+2 .. may stay in flight), then
+    // everyone: tile t+1 readable, stage t % STAGES free for reuse
+    if (more)
+      __builtin_amdgcn_s_waitcnt(VmWait<(STAGES - 2) * LOADS>::imm);
+    else
+      __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
@@ -398,19 +421,9 @@ k_products_direct(const ProductArgs a) {
 
 // ------------------------------------------------------------------ dispatch
 // Tile configurations (edge, k-tile, wave grid, LDS swizzle shift).
-constexpr int kSplitBM = 256, kSplitBK = 32, kSplitWGM = 2, kSplitWGN = 4, kSplitSWZ = 2;
+constexpr int kSplitBM = 256, kSplitWGM = 2, kSplitWGN = 4;
 constexpr int kDirBM = 128, kDirWGM = 2, kDirWGN = 2, kDirSWZ = 1;
 constexpr int kDirBK32 = 32, kDirBK64 = 16;
-
-// Wave layout of the split products (tuning knob DMPT_SPLIT_WAVES = 4 or 8).
-static int split_waves() {
-  static int w = 0;
-  if (w == 0) {
-    const char* e = getenv("DMPT_SPLIT_WAVES");
-    w = (e && atoi(e) == 4) ? 4 : 8;
-  }
-  return w;
-}
 
 int product_tile(dmpt_precision prec) {
   return (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16) ? kSplitBM : kDirBM;
@@ -443,27 +456,28 @@ static hipError_t launch_one(K kernel, int threads, size_t lds_bytes, int wg_per
   return hipGetLastError();
 }
 
+template <typename T16, int BK, int WGM, int WGN, int SWZ, int STAGES>
+static hipError_t launch_split_cfg(const ProductArgs& a, hipStream_t s) {
+  constexpr size_t lds = (size_t)STAGES * (4 * kSplitBM) * (BK / 8) * 16;
+  static_assert(lds <= 160 * 1024, "LDS of one CU");
+  return launch_one(k_products_split<T16, kSplitBM, BK, WGM, WGN, SWZ, STAGES>,
+                    WGM * WGN * kWave, lds, 1, a, s);
+}
+
+template <typename T16>
+static hipError_t launch_split(const ProductArgs& a, hipStream_t s) {
+  return launch_split_cfg<T16, kPanelK, kSplitWGM, kSplitWGN, 2, 2>(a, s);
+}
+
 hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s) {
   // tiles cover [0, kdim)^2 exactly; rows must keep 16-byte alignment
   if (a.kdim % product_tile(prec) != 0 || a.ld < a.kdim || a.ld % 8 != 0)
     return hipErrorInvalidValue;
   switch (prec) {
-    case DMPT_SPLIT_FP16: {
-      constexpr size_t lds = 2 * (4 * kSplitBM) * (kSplitBK / 8) * 16;
-      if (split_waves() == 4)
-        return launch_one(k_products_split<_Float16, kSplitBM, kSplitBK, 2, 2, kSplitSWZ>,
-                          4 * kWave, lds, 1, a, s);
-      return launch_one(k_products_split<_Float16, kSplitBM, kSplitBK, kSplitWGM, kSplitWGN, kSplitSWZ>,
-                        kSplitWGM * kSplitWGN * kWave, lds, 1, a, s);
-    }
-    case DMPT_SPLIT_BF16: {
-      constexpr size_t lds = 2 * (4 * kSplitBM) * (kSplitBK / 8) * 16;
-      if (split_waves() == 4)
-        return launch_one(k_products_split<__bf16, kSplitBM, kSplitBK, 2, 2, kSplitSWZ>,
-                          4 * kWave, lds, 1, a, s);
-      return launch_one(k_products_split<__bf16, kSplitBM, kSplitBK, kSplitWGM, kSplitWGN, kSplitSWZ>,
-                        kSplitWGM * kSplitWGN * kWave, lds, 1, a, s);
-    }
+    case DMPT_SPLIT_FP16:
+      return launch_split<_Float16>(a, s);
+    case DMPT_SPLIT_BF16:
+      return launch_split<__bf16>(a, s);
     case DMPT_FP32: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK32 / 4) * 16;
       return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN, kDirSWZ>,

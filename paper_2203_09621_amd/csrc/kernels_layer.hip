@@ -217,12 +217,19 @@ hipError_t launch_init_s0(dmpt_precision prec, const double* H0, int64_t n, int6
 // master <- src (layer precision); split forms also write hi/lo with scale 2^e.
 template <typename M, typename T16, bool SPLIT>
 __global__ void __launch_bounds__(kBlk) k_load(const M* src, M* master, uint16_t* hi, uint16_t* lo,
-                                              int64_t total, int e, int t) {
+                                              int64_t total, int64_t ld, int64_t kdim, int e,
+                                              int t) {
   for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total;
        q += (int64_t)gridDim.x * kBlk) {
     const M v = src[q];
     master[q] = v;
-    if constexpr (SPLIT) split_one<T16>((float)v, e, t, hi + q, lo + q);
+    if constexpr (SPLIT) {
+      const int64_t r = q / ld, c = q - r * ld;
+      if (c < kdim) {
+        const int64_t pi = panel_index(r, c, kdim);
+        split_one<T16>((float)v, e, t, hi + pi, lo + pi);
+      }
+    }
   }
 }
 
@@ -232,21 +239,23 @@ hipError_t launch_load_s0(dmpt_precision prec, const void* s_init, void* master,
   switch (prec) {
     case DMPT_FP64:
       hipLaunchKernelGGL((k_load<double, _Float16, false>), dim3(4096), dim3(kBlk), 0, s,
-                         (const double*)s_init, (double*)master, nullptr, nullptr, total, 0, 0);
+                         (const double*)s_init, (double*)master, nullptr, nullptr, total, ld, rows,
+                         0, 0);
       break;
     case DMPT_FP32:
       hipLaunchKernelGGL((k_load<float, _Float16, false>), dim3(4096), dim3(kBlk), 0, s,
-                         (const float*)s_init, (float*)master, nullptr, nullptr, total, 0, 0);
+                         (const float*)s_init, (float*)master, nullptr, nullptr, total, ld, rows,
+                         0, 0);
       break;
     case DMPT_SPLIT_FP16:
       hipLaunchKernelGGL((k_load<float, _Float16, true>), dim3(4096), dim3(kBlk), 0, s,
                          (const float*)s_init, (float*)master, (uint16_t*)hi, (uint16_t*)lo, total,
-                         0, t);
+                         ld, rows, 0, t);
       break;
     case DMPT_SPLIT_BF16:
       hipLaunchKernelGGL((k_load<float, __bf16, true>), dim3(4096), dim3(kBlk), 0, s,
                          (const float*)s_init, (float*)master, (uint16_t*)hi, (uint16_t*)lo, total,
-                         0, t);
+                         ld, rows, 0, t);
       break;
   }
   return hipGetLastError();
@@ -287,7 +296,12 @@ __global__ void __launch_bounds__(kBlk) k_init_s1(const double* H1, int64_t n, i
     if (r < n && c < n) v = -H1[r * n + c] / w;
     const M mv = (M)v;
     s1[q] = mv;
-    if constexpr (SPLIT) split_one<T16>((float)mv, e, t, hi + q, lo + q);
+    if constexpr (SPLIT) {
+      if (c < rows) {
+        const int64_t pi = panel_index(r, c, rows);
+        split_one<T16>((float)mv, e, t, hi + pi, lo + pi);
+      }
+    }
   }
 }
 
@@ -429,8 +443,8 @@ hipError_t launch_decide0(dmpt_precision prec, LayerState* st, const void* x, in
 template <typename M, typename T16, bool SPLIT>
 __global__ void __launch_bounds__(kBlk) k_update(const LayerState* st, int which, const M* x,
                                                 const M* s_old, M* dst, uint16_t* hi,
-                                                uint16_t* lo, int64_t total, int t, double* pfro,
-                                                double* pmax) {
+                                                uint16_t* lo, int64_t total, int64_t ld,
+                                                int64_t kdim, int t, double* pfro, double* pmax) {
   if (st->done) return;
   const int sig = st->sigma_cur;
   bool active, want_fro;
@@ -466,12 +480,17 @@ __global__ void __launch_bounds__(kBlk) k_update(const LayerState* st, int which
 #pragma unroll
       for (int r = 0; r < 4; ++r) mx = fmax(mx, fabs((double)nv[r]));
       if constexpr (SPLIT) {
-        uint16_t h[4], l[4];
+        // four consecutive columns of one row (ld % 4 == 0) stay inside one panel block
+        const int64_t row = (4 * q) / ld, col = 4 * q - row * ld;
+        if (col < kdim) {
+          uint16_t h[4], l[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) split_one<T16>((float)nv[r], e, t, h + r, l + r);
-        typedef uint16_t U4 __attribute__((ext_vector_type(4)));
-        ((U4*)hi)[q] = U4{h[0], h[1], h[2], h[3]};
-        ((U4*)lo)[q] = U4{l[0], l[1], l[2], l[3]};
+          for (int r = 0; r < 4; ++r) split_one<T16>((float)nv[r], e, t, h + r, l + r);
+          typedef uint16_t U4 __attribute__((ext_vector_type(4)));
+          const int64_t pi = panel_index(row, col, kdim) / 4;
+          ((U4*)hi)[pi] = U4{h[0], h[1], h[2], h[3]};
+          ((U4*)lo)[pi] = U4{l[0], l[1], l[2], l[3]};
+        }
       }
     }
   }
@@ -484,29 +503,29 @@ __global__ void __launch_bounds__(kBlk) k_update(const LayerState* st, int which
 }
 
 hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, const void* x,
-                         const void* s_old, void* dst, void* hi, void* lo, int64_t elems, int t,
-                         double* pfro, double* pmax, hipStream_t s) {
-  const int64_t total = elems;
+                         const void* s_old, void* dst, void* hi, void* lo, int64_t rows,
+                         int64_t ld, int t, double* pfro, double* pmax, hipStream_t s) {
+  const int64_t total = rows * ld;
   switch (prec) {
     case DMPT_FP64:
       hipLaunchKernelGGL((k_update<double, _Float16, false>), dim3(kRedBlocks), dim3(kBlk), 0, s, st,
                          which, (const double*)x, (const double*)s_old, (double*)dst, nullptr,
-                         nullptr, total, t, pfro, pmax);
+                         nullptr, total, ld, rows, t, pfro, pmax);
       break;
     case DMPT_FP32:
       hipLaunchKernelGGL((k_update<float, _Float16, false>), dim3(kRedBlocks), dim3(kBlk), 0, s, st,
                          which, (const float*)x, (const float*)s_old, (float*)dst, nullptr, nullptr,
-                         total, t, pfro, pmax);
+                         total, ld, rows, t, pfro, pmax);
       break;
     case DMPT_SPLIT_FP16:
       hipLaunchKernelGGL((k_update<float, _Float16, true>), dim3(kRedBlocks), dim3(kBlk), 0, s, st,
                          which, (const float*)x, (const float*)s_old, (float*)dst, (uint16_t*)hi,
-                         (uint16_t*)lo, total, t, pfro, pmax);
+                         (uint16_t*)lo, total, ld, rows, t, pfro, pmax);
       break;
     case DMPT_SPLIT_BF16:
       hipLaunchKernelGGL((k_update<float, __bf16, true>), dim3(kRedBlocks), dim3(kBlk), 0, s, st,
                          which, (const float*)x, (const float*)s_old, (float*)dst, (uint16_t*)hi,
-                         (uint16_t*)lo, total, t, pfro, pmax);
+                         (uint16_t*)lo, total, ld, rows, t, pfro, pmax);
       break;
   }
   return hipGetLastError();
@@ -645,7 +664,12 @@ __global__ void __launch_bounds__(kBlk) k_from_f64(const double* A, int64_t n, i
     const int64_t i = q / ld, j = q - i * ld;
     const M v = (i < n && j < n) ? (M)A[i * n + j] : (M)0;
     master[q] = v;
-    if constexpr (SPLIT) split_one<T16>((float)v, e, t, hi + q, lo + q);
+    if constexpr (SPLIT) {
+      if (j < rows) {
+        const int64_t pi = panel_index(i, j, rows);
+        split_one<T16>((float)v, e, t, hi + pi, lo + pi);
+      }
+    }
   }
 }
 

@@ -60,6 +60,7 @@ typedef enum {
 } dmpt_precision;
 
 #define DMPT_MAX_K 8          /* most perturbations per context */
+#define DMPT_MAX_KB 3         /* most perturbations per problem of a batch */
 #define DMPT_MAX_LAYERS 256   /* hard cap on the layer count */
 
 typedef struct {
@@ -71,6 +72,8 @@ typedef struct {
                               context's stream (dmpt_stats.product_ms / product_launches) */
   int32_t ckpt_every;      /* > 0: dmpt_response keeps (S, S1) every this many layers so that
                               dmpt_adjoint can run; 0 (default): no adjoint workspace */
+  int32_t graph;           /* batched solves: nonzero (default) captures the whole response in
+                              one HIP graph on first use and replays it */
 } dmpt_options;
 
 typedef struct {
@@ -134,6 +137,53 @@ dmpt_status dmpt_adjoint(dmpt_ctx* ctx, const double* const* W, int32_t k, doubl
 
 /* Release the context and its workspace.  NULL is allowed. */
 void dmpt_destroy(dmpt_ctx* ctx);
+
+/* ---- batched solves: many independent problems of different sizes ----
+ * Algorithms 1-3 for `count` problems at once.  Problem p has N[p] orbitals,
+ * Nocc[p] occupied states and k[p] in [1, DMPT_MAX_KB] perturbations.  All
+ * problems advance layer by layer together; each keeps its own sigma
+ * sequence and stopping tests and stops on its own.  Split precisions only
+ * (DMPT_SPLIT_BF16 / DMPT_SPLIT_FP16).  The tile size of each problem's
+ * products (256 or 128 rows) is chosen at init by timing candidate size
+ * thresholds on this batch.  With options.graph (default) the whole response
+ * (normalisation, every layer up to max_layers, outputs) is one HIP graph,
+ * captured on the first dmpt_batch_response and replayed afterwards. */
+typedef struct dmpt_batch dmpt_batch;
+
+typedef struct {
+  int32_t layers;                  /* layers run by this problem */
+  int32_t d0_layer;
+  int32_t converged;
+  int32_t k;
+  int32_t d1_layer[DMPT_MAX_KB];
+  int32_t pad;
+  double idem0;                    /* ||P0 - P0^2||_F at the D0 layer */
+  double idem1[DMPT_MAX_KB];       /* first-order idempotency residual at the D1 layer */
+} dmpt_problem_stats;
+
+/* Allocate the workspace of a batch and tune its tiles.  N, Nocc, k: host
+ * arrays of `count` entries.  Errors: EINVAL, ENOMEM, EHIP, ENOTSUP. */
+dmpt_status dmpt_batch_init(dmpt_batch** batch, int32_t count, const int64_t* N,
+                            const int64_t* Nocc, const int32_t* k,
+                            const dmpt_options* opt /* NULL = defaults */, void* stream);
+
+/* Solve every problem.  H0[p] (count entries) and H1[i] (sum of k entries,
+ * problem-major) are host arrays of device FP64 pointers; P0[p] (may be NULL
+ * as a whole or per entry) and P1[i] receive the results (device FP64, N x N
+ * of their problem).  st (count entries, may be NULL) receives per-problem
+ * statistics, ms (may be NULL) the device time.  Returns ENOCONV if some
+ * problem hit the layer cap, ENONFINITE on a non-finite value. */
+dmpt_status dmpt_batch_response(dmpt_batch* batch, const double* const* H0,
+                                const double* const* H1, double* const* P0, double* const* P1,
+                                dmpt_problem_stats* st, double* ms);
+
+/* Tile classes the autotuner chose: problems with padded size <= *threshold
+ * use 128-row tiles; number of tile items of each class. */
+dmpt_status dmpt_batch_info(const dmpt_batch* batch, int32_t* threshold, int32_t* n_items_256,
+                            int32_t* n_items_128);
+
+/* Release a batch.  NULL is allowed. */
+void dmpt_batch_destroy(dmpt_batch* batch);
 
 /* Short name of a status code (static storage). */
 const char* dmpt_status_str(dmpt_status s);

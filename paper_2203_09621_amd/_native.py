@@ -22,7 +22,8 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
-           "dmpt_adjoint", "dmpt_destroy",
+           "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
+           "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
            "dmpt_selftest_mfma"]
 
@@ -30,7 +31,7 @@ EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_re
 class DmptOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_layers", c_int32),
                 ("check_symmetry", c_int32), ("poll_every", c_int32), ("timing", c_int32),
-                ("ckpt_every", c_int32)]
+                ("ckpt_every", c_int32), ("graph", c_int32)]
 
 
 class DmptStats(ctypes.Structure):
@@ -53,6 +54,18 @@ class DmptStats(ctypes.Structure):
             "product_ms": self.product_ms, "product_launches": self.product_launches,
             "x_layers": self.x_layers,
         }
+
+
+class DmptProblemStats(ctypes.Structure):
+    _fields_ = [("layers", c_int32), ("d0_layer", c_int32), ("converged", c_int32), ("k", c_int32),
+                ("d1_layer", c_int32 * 3), ("pad", c_int32), ("idem0", c_double),
+                ("idem1", c_double * 3)]
+
+    def as_dict(self) -> dict:
+        k = self.k
+        return {"layers": self.layers, "d0_layer": self.d0_layer,
+                "converged": bool(self.converged), "k": k, "d1_layer": list(self.d1_layer[:k]),
+                "idem0": self.idem0, "idem1": list(self.idem1[:k])}
 
 
 class DmptError(RuntimeError):
@@ -80,6 +93,17 @@ def _load():
     lib.dmpt_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
                                  POINTER(c_void_p), POINTER(DmptStats)]
     lib.dmpt_adjoint.restype = c_int32
+    lib.dmpt_batch_init.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_int64), POINTER(c_int64),
+                                    POINTER(c_int32), POINTER(DmptOptions), c_void_p]
+    lib.dmpt_batch_init.restype = c_int32
+    lib.dmpt_batch_response.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p),
+                                        POINTER(c_void_p), POINTER(c_void_p),
+                                        POINTER(DmptProblemStats), POINTER(c_double)]
+    lib.dmpt_batch_response.restype = c_int32
+    lib.dmpt_batch_info.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]
+    lib.dmpt_batch_info.restype = c_int32
+    lib.dmpt_batch_destroy.argtypes = [c_void_p]
+    lib.dmpt_batch_destroy.restype = None
     lib.dmpt_destroy.argtypes = [c_void_p]
     lib.dmpt_destroy.restype = None
     lib.dmpt_status_str.argtypes = [c_int32]
@@ -222,6 +246,53 @@ def dmpt_selftest_mfma(stream=None) -> int:
     if status not in (0, -7):
         _check(status)
     return detail.value
+
+
+def dmpt_batch_init(Ns, noccs, ks, precision: str = "split_bf16", max_layers: int = 100,
+                    graph: bool = True, stream=None) -> c_void_p:
+    """dmpt_batch_init: workspace and tile tuning for a batch of problems."""
+    count = len(Ns)
+    o = default_options()
+    o.precision = PRECISION[precision]
+    o.max_layers = max_layers
+    o.graph = int(graph)
+    b = c_void_p()
+    _check(LIB.dmpt_batch_init(byref(b), count, (c_int64 * count)(*Ns), (c_int64 * count)(*noccs),
+                               (c_int32 * count)(*ks), byref(o), _stream(stream)))
+    return b
+
+
+def dmpt_batch_response(batch: c_void_p, H0s, H1s, P0s=None, P1s=None):
+    """dmpt_batch_response: H0s a list of device tensors, H1s a list (per problem)
+    of lists of device tensors.  Returns (P0s, P1s, per-problem stats, ms)."""
+    torch = _torch()
+    count = len(H0s)
+    flat_h1 = [h for hs in H1s for h in hs]
+    if P0s is None:
+        P0s = [torch.empty_like(h) for h in H0s]
+    if P1s is None:
+        P1s = [[torch.empty_like(h) for h in hs] for hs in H1s]
+    flat_p1 = [p for ps in P1s for p in ps]
+    st = (DmptProblemStats * count)()
+    ms = c_double(0.0)
+    status = LIB.dmpt_batch_response(
+        batch, (c_void_p * count)(*[_dev(h, "H0").value for h in H0s]),
+        (c_void_p * len(flat_h1))(*[_dev(h, "H1").value for h in flat_h1]),
+        (c_void_p * count)(*[_dev(p, "P0").value for p in P0s]),
+        (c_void_p * len(flat_p1))(*[_dev(p, "P1").value for p in flat_p1]), st, byref(ms))
+    stats = [x.as_dict() for x in st]
+    _check(status, {"problems": stats})
+    return P0s, P1s, stats, ms.value
+
+
+def dmpt_batch_info(batch: c_void_p):
+    th, n256, n128 = c_int32(), c_int32(), c_int32()
+    _check(LIB.dmpt_batch_info(batch, byref(th), byref(n256), byref(n128)))
+    return th.value, n256.value, n128.value
+
+
+def dmpt_batch_destroy(batch: c_void_p) -> None:
+    LIB.dmpt_batch_destroy(batch)
 
 
 def solve(H0, H1s, nocc: int, precision: str = "split_fp16", max_layers: int = 100, **kw):

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdmpt.so")
-SOURCES = ["kernels_gemm.hip", "kernels_layer.hip", "kernels_adjoint.hip", "dmpt_api.hip"]
+SOURCES = ["kernels_gemm.hip", "kernels_layer.hip", "kernels_adjoint.hip", "dmpt_api.hip",
+           "dmpt_batch.hip"]
 ARCH = "gfx950"
 
 

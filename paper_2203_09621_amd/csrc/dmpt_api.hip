@@ -25,6 +25,12 @@ dmpt_status fail(dmpt_status s, const std::string& msg) {
   return s;
 }
 
+}  // namespace
+
+void dmpt::set_last_error(const char* msg) { g_err = msg; }
+
+namespace {
+
 #define HIPCHK(expr)                                                                     \
   do {                                                                                   \
     hipError_t _e = (expr);                                                              \
@@ -64,7 +70,7 @@ std::vector<TileItem> build_items(int T, int k) {
         for (int ti = g0; ti < std::min(g1, tj + 1); ++ti) {
           TileItem it;
           it.out = (int16_t)out;
-          it.pad = 0;
+          it.prob = 0;
           it.ti = ti;
           it.tj = tj;
           v.push_back(it);
@@ -206,6 +212,7 @@ void dmpt_default_options(dmpt_options* opt) {
   opt->poll_every = 0;
   opt->timing = 0;
   opt->ckpt_every = 0;
+  opt->graph = 1;
 }
 
 const char* dmpt_status_str(dmpt_status s) {

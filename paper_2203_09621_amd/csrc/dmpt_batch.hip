@@ -1,0 +1,723 @@
+// Batched DNN-SP2-PT: many independent Hamiltonians of different sizes run
+// Algorithms 1-3 together.  All problems advance layer by layer: one
+// persistent product launch per tile class covers the tiles of every problem
+// still running, the decisions run as one workgroup per problem, and the
+// fused updates walk a block table of (problem, matrix, chunk) entries.  Each
+// problem keeps its own LayerState, so problems stop independently; kernels
+// skip problems that are done.  The whole response (normalisation, every
+// layer up to the cap, outputs) is captured once into a HIP graph and
+// replayed; inputs and outputs reach the graph through device pointer tables.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "layer_common.h"
+
+namespace dmpt {
+
+struct BatchProblem {
+  LayerState* st;
+  float* s_master;
+  uint16_t* s_hi;
+  uint16_t* s_lo;
+  float* x;
+  float* s1buf[kMaxKB][2];
+  uint16_t* s1_hi[kMaxKB];
+  uint16_t* s1_lo[kMaxKB];
+  int64_t n, np, ld;
+  double nocc;
+  int32_t k;
+  int32_t h0_index, h1_first;        // positions in the input / output pointer tables
+  int32_t u0_first, u0_count;        // S0 block-table range
+  int32_t u1_first[kMaxKB], u1_count[kMaxKB];
+};
+
+struct Chunk {
+  int32_t p, j;                      // problem, matrix (-1: S0, j: S1_j)
+  int64_t q0, q1;                    // range of 4-element vectors of the padded storage
+};
+
+struct ProblemSummary {
+  int32_t layers, d0_layer, converged, error;
+  int32_t d1_layer[kMaxKB];
+  int32_t pad;
+  double idem0;
+  double idem1[kMaxKB];
+};
+
+constexpr int kChunkVec = 4 * kBlk;  // vectors per block-table chunk (16 K elements)
+
+// ------------------------------------------------------------------ normalisation
+// Per problem: clear the state, Gershgorin bounds of H0 (one wave per row),
+// N_S = Tr S0, and the Algorithm 1-3 scalars.
+__global__ void __launch_bounds__(kBlk) k_b_setup(BatchProblem* P, const double* const* h0tab,
+                                                 int max_layers) {
+  BatchProblem& b = P[blockIdx.x];
+  LayerState* st = b.st;
+  {
+    int32_t* w = (int32_t*)st;
+    for (size_t i = threadIdx.x; i < sizeof(LayerState) / 4; i += kBlk) w[i] = 0;
+  }
+  __syncthreads();
+  const double* H = h0tab[b.h0_index];
+  const int64_t n = b.n;
+  const int lane = threadIdx.x & (kWave - 1);
+  double lo = INFINITY, hi = -INFINITY, tr = 0.0;
+  for (int64_t i = threadIdx.x / kWave; i < n; i += kBlk / kWave) {
+    const double* row = H + i * n;
+    double r = 0.0;
+    for (int64_t j = lane; j < n; j += kWave) r += (j == i) ? 0.0 : fabs(row[j]);
+    r = wave_sum(r);
+    const double d = row[i];
+    lo = fmin(lo, d - r);
+    hi = fmax(hi, d + r);
+    tr += (lane == 0) ? d : 0.0;
+  }
+  lo = block_min(lo);
+  hi = block_max(hi);
+  tr = block_sum(tr);
+  if (threadIdx.x != 0) return;
+  const double w = hi - lo;
+  st->n_real = (int32_t)n;
+  st->k = b.k;
+  st->max_layers = max_layers;
+  st->nocc = b.nocc;
+  st->eps1 = lo;
+  st->epsN = hi;
+  st->n_s0 = ((double)n * hi - tr) / w;
+  st->n_s = st->n_s0;
+  for (int j = 0; j < kMaxK; ++j) st->d1[j] = j < b.k ? 0 : 1;
+  if (!(w > 0.0) || !isfinite(w)) {
+    st->error = DMPT_ENONFINITE;
+    st->done = 1;
+  }
+}
+
+// max |H1_j| per chunk of problem p, response j.
+__global__ void __launch_bounds__(kBlk) k_b_maxabs1(const BatchProblem* P, const Chunk* C,
+                                                   const double* const* h1tab, double* part) {
+  const Chunk c = C[blockIdx.x];
+  const BatchProblem& b = P[c.p];
+  const double* H = h1tab[b.h1_first + c.j];
+  double m = 0.0;
+  for (int64_t q = c.q0 * 4 + threadIdx.x; q < c.q1 * 4; q += kBlk) {
+    const int64_t r = q / b.ld, col = q - r * b.ld;
+    if (r < b.n && col < b.n) {
+      const double v = fabs(H[r * b.n + col]);
+      m = (v > m || v != v) ? v : m;
+    }
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// Split scale of S1_0 = -H1/(eps_N - eps_1) per response.
+__global__ void __launch_bounds__(kBlk) k_b_s1setup(const BatchProblem* P, const double* part) {
+  const BatchProblem& b = P[blockIdx.x];
+  LayerState* st = b.st;
+  for (int j = 0; j < b.k; ++j) {
+    double m = 0.0;
+    for (int i = threadIdx.x; i < b.u1_count[j]; i += kBlk) {
+      const double v = part[b.u1_first[j] + i];
+      m = (v > m || v != v) ? v : m;
+    }
+    m = block_max(m);
+    if (threadIdx.x == 0) {
+      const double mx = m / (st->epsN - st->eps1);
+      if (!isfinite(mx)) {
+        st->error = DMPT_ENONFINITE;
+        st->done = 1;
+      }
+      const int e = split_exponent(mx);
+      st->s1_exp_split[j] = e;
+      st->s1_exp_next[j] = e;
+      st->s1_exp_hist[j][0] = e;
+      st->s1_max[j] = mx;
+    }
+  }
+}
+
+// S0 = (eps_N I - H0)/(eps_N - eps_1) (j = -1) or S1_0 = -H1_j/(eps_N - eps_1),
+// FP32 master plus panel-major hi/lo.
+template <typename T16>
+__global__ void __launch_bounds__(kBlk) k_b_init(const BatchProblem* P, const Chunk* C,
+                                                const double* const* h0tab,
+                                                const double* const* h1tab, int t) {
+  const Chunk c = C[blockIdx.x];
+  const BatchProblem& b = P[c.p];
+  const LayerState* st = b.st;
+  const double en = st->epsN, w = st->epsN - st->eps1;
+  const double* H = c.j < 0 ? h0tab[b.h0_index] : h1tab[b.h1_first + c.j];
+  float* m = c.j < 0 ? b.s_master : b.s1buf[c.j][0];
+  uint16_t* hi = c.j < 0 ? b.s_hi : b.s1_hi[c.j];
+  uint16_t* lo = c.j < 0 ? b.s_lo : b.s1_lo[c.j];
+  const int e = c.j < 0 ? 0 : st->s1_exp_split[c.j];
+  for (int64_t q = c.q0 * 4 + threadIdx.x; q < c.q1 * 4; q += kBlk) {
+    const int64_t r = q / b.ld, col = q - r * b.ld;
+    double v = 0.0;
+    if (r < b.n && col < b.n) v = c.j < 0 ? ((r == col ? en : 0.0) - H[r * b.n + col]) / w
+                                          : -H[r * b.n + col] / w;
+    const float f = (float)v;
+    m[q] = f;
+    if (col < b.np) {
+      const int64_t pi = panel_index(r, col, b.np);
+      split_one<T16>(f, e, t, hi + pi, lo + pi);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ layer kernels
+__global__ void __launch_bounds__(kBlk) k_b_decide0(const BatchProblem* P) {
+  const BatchProblem& b = P[blockIdx.x];
+  decide0_body<float>(b.st, b.x, b.ld);
+}
+
+template <typename T16>
+__global__ void __launch_bounds__(kBlk) k_b_update(const BatchProblem* P, const Chunk* C,
+                                                  double* pfro, double* pmax, int t, int layer) {
+  const Chunk c = C[blockIdx.x];
+  const BatchProblem& b = P[c.p];
+  const int64_t q0 = c.q0 + threadIdx.x;
+  if (c.j < 0) {
+    update_body<float, T16, true>(b.st, -1, b.x, b.s_master, b.s_master, b.s_hi, b.s_lo, q0, c.q1,
+                                  kBlk, b.ld, b.np, t, pfro + blockIdx.x, nullptr);
+  } else {
+    const int cur = layer & 1;
+    float* s1 = b.s1buf[c.j][cur];
+    update_body<float, T16, true>(b.st, c.j, s1, b.s1buf[c.j][cur ^ 1], s1, b.s1_hi[c.j],
+                                  b.s1_lo[c.j], q0, c.q1, kBlk, b.ld, b.np, t, pfro + blockIdx.x,
+                                  pmax + blockIdx.x);
+  }
+}
+
+__global__ void __launch_bounds__(kBlk) k_b_decide1(const BatchProblem* P, const double* p0,
+                                                   const double* p1f, const double* p1m, int t) {
+  const BatchProblem& b = P[blockIdx.x];
+  Partials pr;
+  pr.fro0 = p0 + b.u0_first;
+  pr.n0 = b.u0_count;
+  for (int j = 0; j < kMaxK; ++j) {
+    pr.fro1[j] = j < b.k ? p1f + b.u1_first[j] : p1f;
+    pr.max1[j] = j < b.k ? p1m + b.u1_first[j] : p1m;
+    pr.n1[j] = j < b.k ? b.u1_count[j] : 0;
+  }
+  decide1_body(b.st, pr, 1, t);
+}
+
+// ------------------------------------------------------------------ outputs
+__global__ void __launch_bounds__(kBlk) k_b_out(const BatchProblem* P, const Chunk* C,
+                                               double* const* p0tab, double* const* p1tab) {
+  const Chunk c = C[blockIdx.x];
+  const BatchProblem& b = P[c.p];
+  const LayerState* st = b.st;
+  const float* src;
+  double* dst;
+  if (c.j < 0) {
+    src = b.s_master;
+    dst = p0tab[b.h0_index];
+  } else {
+    const int L = st->d1[c.j] && st->d1_layer[c.j] > 0 ? st->d1_layer[c.j] - 1 : st->n;
+    src = b.s1buf[c.j][L & 1];
+    dst = p1tab[b.h1_first + c.j];
+  }
+  if (!dst) return;
+  for (int64_t q = c.q0 * 4 + threadIdx.x; q < c.q1 * 4; q += kBlk) {
+    const int64_t r = q / b.ld, col = q - r * b.ld;
+    if (r < b.n && col < b.n) dst[r * b.n + col] = (double)src[q];
+  }
+}
+
+__global__ void k_b_summary(const BatchProblem* P, ProblemSummary* out) {
+  if (threadIdx.x != 0) return;
+  const BatchProblem& b = P[blockIdx.x];
+  const LayerState* st = b.st;
+  ProblemSummary s;
+  s.layers = st->n;
+  s.d0_layer = st->d0_layer;
+  s.converged = st->converged;
+  s.error = st->error;
+  s.pad = 0;
+  s.idem0 = st->fro0;
+  for (int j = 0; j < kMaxKB; ++j) {
+    s.d1_layer[j] = j < b.k ? st->d1_layer[j] : 0;
+    s.idem1[j] = (j < b.k && st->d1_layer[j] > 0) ? st->fro1[j][st->d1_layer[j]] : 0.0;
+  }
+  out[blockIdx.x] = s;
+}
+
+}  // namespace dmpt
+
+// ====================================================================== host side
+using namespace dmpt;
+
+namespace {
+
+dmpt_status bfail(dmpt_status s, const std::string& m) {
+  set_last_error(m.c_str());
+  return s;
+}
+
+#define BCHK(expr)                                                                      \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return bfail(DMPT_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+std::vector<TileItem> triangle_items(int T, int k, int prob) {
+  std::vector<TileItem> v;
+  const int GR = 8;
+  auto add_out = [&](int out) {
+    for (int g0 = 0; g0 < T; g0 += GR) {
+      const int g1 = std::min(T, g0 + GR);
+      for (int tj = g0; tj < T; ++tj)
+        for (int ti = g0; ti < std::min(g1, tj + 1); ++ti) {
+          TileItem it;
+          it.out = (int16_t)out;
+          it.prob = (int16_t)prob;
+          it.ti = ti;
+          it.tj = tj;
+          v.push_back(it);
+        }
+    }
+  };
+  for (int j = 0; j < k; ++j) add_out(1 + j);
+  add_out(0);
+  return v;
+}
+
+}  // namespace
+
+struct dmpt_batch {
+  int count;
+  dmpt_precision prec;
+  int t;
+  int max_layers;
+  int use_graph;
+  hipStream_t stream;
+  hipStream_t cap;
+  std::vector<BatchProblem> hp;
+  BatchProblem* dp = nullptr;
+  std::vector<Chunk> c0, c1;
+  Chunk* dc0 = nullptr;
+  Chunk* dc1 = nullptr;
+  double* part0 = nullptr;
+  double* part1f = nullptr;
+  double* part1m = nullptr;
+  ProblemDesc* desc[2] = {nullptr, nullptr};   // by layer parity
+  int threshold = 0;                           // problems with Np <= threshold use 128-row tiles
+  TileItem* items[2] = {nullptr, nullptr};     // [0]: 256-row tiles, [1]: 128-row tiles
+  int n_items[2] = {0, 0};
+  int total_k = 0;
+  const double** h0tab = nullptr;
+  const double** h1tab = nullptr;
+  double** p0tab = nullptr;
+  double** p1tab = nullptr;
+  void** host_tab = nullptr;                   // pinned staging of the four tables
+  ProblemSummary* dsum = nullptr;
+  ProblemSummary* hsum = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<void*> allocs;
+  std::vector<double> tune_ms;                 // autotuner timings per candidate threshold
+  std::vector<int> tune_cand;
+};
+
+namespace {
+
+hipError_t balloc(dmpt_batch* b, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) b->allocs.push_back(*p);
+  return e;
+}
+
+void batch_free(dmpt_batch* b) {
+  if (!b) return;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (void* p : b->allocs) hipFree(p);
+  if (b->host_tab) hipHostFree(b->host_tab);
+  if (b->hsum) hipHostFree(b->hsum);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->ev0) hipEventDestroy(b->ev0);
+  if (b->ev1) hipEventDestroy(b->ev1);
+  delete b;
+}
+
+// Item lists of the two tile classes for a given threshold.
+hipError_t build_class_items(dmpt_batch* b, int threshold, bool upload) {
+  std::vector<TileItem> big, small;
+  for (int p = 0; p < b->count; ++p) {
+    const BatchProblem& bp = b->hp[p];
+    const bool sm = bp.np <= threshold;
+    const int tile = sm ? 128 : 256;
+    const int T = (int)((bp.n + tile - 1) / tile);
+    std::vector<TileItem> v = triangle_items(T, bp.k, p);
+    (sm ? small : big).insert((sm ? small : big).end(), v.begin(), v.end());
+  }
+  b->threshold = threshold;
+  b->n_items[0] = (int)big.size();
+  b->n_items[1] = (int)small.size();
+  if (!upload) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (!big.empty())
+    e = hipMemcpy(b->items[0], big.data(), big.size() * sizeof(TileItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !small.empty())
+    e = hipMemcpy(b->items[1], small.data(), small.size() * sizeof(TileItem),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  // the k extent of each problem follows its class
+  std::vector<ProblemDesc> d[2];
+  for (int par = 0; par < 2; ++par) {
+    d[par].resize(b->count);
+    for (int p = 0; p < b->count; ++p) {
+      const BatchProblem& bp = b->hp[p];
+      ProblemDesc& q = d[par][p];
+      memset(&q, 0, sizeof(q));
+      q.s_hi = bp.s_hi;
+      q.s_lo = bp.s_lo;
+      for (int j = 0; j < bp.k; ++j) {
+        q.s1_hi[j] = bp.s1_hi[j];
+        q.s1_lo[j] = bp.s1_lo[j];
+        q.x1[j] = bp.s1buf[j][par];
+      }
+      q.x = bp.x;
+      q.state = bp.st;
+      q.ld = bp.ld;
+      const int tile = bp.np <= threshold ? 128 : 256;
+      q.kdim = (bp.n + tile - 1) / tile * tile;
+      q.pdim = bp.np;
+    }
+    e = hipMemcpy(b->desc[par], d[par].data(), b->count * sizeof(ProblemDesc),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_products_all(dmpt_batch* b, int parity, bool with_state, hipStream_t s) {
+  (void)with_state;
+  ProductArgs a;
+  memset(&a, 0, sizeof(a));
+  a.probs = b->desc[parity];
+  a.lo_shift = b->t;
+  hipError_t e = hipSuccess;
+  if (b->n_items[0] > 0) {
+    a.items = b->items[0];
+    a.n_items = b->n_items[0];
+    e = launch_products_batch(b->prec, 256, a, s);
+  }
+  if (e == hipSuccess && b->n_items[1] > 0) {
+    a.items = b->items[1];
+    a.n_items = b->n_items[1];
+    e = launch_products_batch(b->prec, 128, a, s);
+  }
+  return e;
+}
+
+template <typename T16>
+hipError_t enqueue_response(dmpt_batch* b, hipStream_t s) {
+  const int P = b->count;
+  hipLaunchKernelGGL(k_b_setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->h0tab, b->max_layers);
+  if (!b->c1.empty()) {
+    hipLaunchKernelGGL(k_b_maxabs1, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1,
+                       b->h1tab, b->part1m);
+    hipLaunchKernelGGL(k_b_s1setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->part1m);
+  }
+  hipLaunchKernelGGL(k_b_init<T16>, dim3(b->c0.size()), dim3(kBlk), 0, s, b->dp, b->dc0, b->h0tab,
+                     b->h1tab, b->t);
+  if (!b->c1.empty())
+    hipLaunchKernelGGL(k_b_init<T16>, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1,
+                       b->h0tab, b->h1tab, b->t);
+  hipError_t e = hipGetLastError();
+  for (int n = 1; n <= b->max_layers && e == hipSuccess; ++n) {
+    e = launch_products_all(b, n & 1, true, s);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_b_decide0, dim3(P), dim3(kBlk), 0, s, b->dp);
+    hipLaunchKernelGGL(k_b_update<T16>, dim3(b->c0.size()), dim3(kBlk), 0, s, b->dp, b->dc0,
+                       b->part0, (double*)nullptr, b->t, n);
+    if (!b->c1.empty())
+      hipLaunchKernelGGL(k_b_update<T16>, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1,
+                         b->part1f, b->part1m, b->t, n);
+    hipLaunchKernelGGL(k_b_decide1, dim3(P), dim3(kBlk), 0, s, b->dp, b->part0, b->part1f,
+                       b->part1m, b->t);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_out, dim3(b->c0.size()), dim3(kBlk), 0, s, b->dp, b->dc0, b->p0tab,
+                     b->p1tab);
+  if (!b->c1.empty())
+    hipLaunchKernelGGL(k_b_out, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1, b->p0tab,
+                       b->p1tab);
+  hipLaunchKernelGGL(k_b_summary, dim3(P), dim3(kWave), 0, s, b->dp, b->dsum);
+  return hipGetLastError();
+}
+
+hipError_t enqueue(dmpt_batch* b, hipStream_t s) {
+  return b->prec == DMPT_SPLIT_FP16 ? enqueue_response<_Float16>(b, s)
+                                    : enqueue_response<__bf16>(b, s);
+}
+
+// Tile-class autotuner: time one product sweep over the whole batch for each
+// candidate threshold (problems with padded size <= threshold use 128-row
+// tiles) and keep the fastest.  Operands are the zero-initialised workspace;
+// MFMA timing does not depend on the values.
+hipError_t autotune(dmpt_batch* b) {
+  int maxnp = 0;
+  for (auto& p : b->hp) maxnp = std::max<int>(maxnp, (int)p.np);
+  std::vector<int> cand = {0};
+  for (int th = 256; th <= maxnp; th += 256) cand.push_back(th);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return e;
+  double best = 1e30;
+  int best_th = 0;
+  b->tune_ms.clear();
+  b->tune_cand = cand;
+  for (int th : cand) {
+    e = build_class_items(b, th, true);
+    if (e != hipSuccess) break;
+    e = launch_products_all(b, 0, false, b->stream);      // warm-up
+    if (e != hipSuccess) break;
+    e = hipEventRecord(e0, b->stream);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_products_all(b, r & 1, false, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e != hipSuccess) break;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    b->tune_ms.push_back(ms / 3.0);
+    if (ms < best) {
+      best = ms;
+      best_th = th;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  return build_class_items(b, best_th, true);
+}
+
+}  // namespace
+
+extern "C" {
+
+dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, const int64_t* Nocc,
+                            const int32_t* k, const dmpt_options* opt_in, void* stream) {
+  if (!out) return bfail(DMPT_EINVAL, "batch pointer is NULL");
+  *out = nullptr;
+  if (count < 1 || count > 32767 || !N || !Nocc || !k) return bfail(DMPT_EINVAL, "bad batch");
+  dmpt_options opt;
+  dmpt_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.precision != DMPT_SPLIT_FP16 && opt.precision != DMPT_SPLIT_BF16)
+    return bfail(DMPT_ENOTSUP, "batched solves run the split precisions only");
+  if (opt.max_layers <= 0) opt.max_layers = 100;
+  if (opt.max_layers > kMaxLayers) return bfail(DMPT_EINVAL, "max_layers above DMPT_MAX_LAYERS");
+  for (int p = 0; p < count; ++p) {
+    if (N[p] < 1 || N[p] > 65536) return bfail(DMPT_EINVAL, "N out of range");
+    if (Nocc[p] <= 0 || Nocc[p] >= N[p]) return bfail(DMPT_EINVAL, "need 0 < Nocc < N");
+    if (k[p] < 1 || k[p] > kMaxKB) return bfail(DMPT_EINVAL, "k out of [1, 3]");
+  }
+  dmpt_batch* b = new dmpt_batch();
+  b->count = count;
+  b->prec = (dmpt_precision)opt.precision;
+  b->t = b->prec == DMPT_SPLIT_FP16 ? kLoShiftF16 : kLoShiftBF16;
+  b->max_layers = opt.max_layers;
+  b->use_graph = opt.graph;
+  b->stream = (hipStream_t)stream;
+  auto bail = [&](dmpt_status s, const std::string& m) {
+    batch_free(b);
+    return bfail(s, m);
+  };
+  // sizes, block tables, sub-allocation offsets
+  b->hp.resize(count);
+  size_t f32 = 0, u16 = 0;
+  int h1 = 0;
+  for (int p = 0; p < count; ++p) {
+    BatchProblem& q = b->hp[p];
+    memset(&q, 0, sizeof(q));
+    q.n = N[p];
+    q.np = (N[p] + 255) / 256 * 256;
+    q.ld = q.np;
+    q.nocc = (double)Nocc[p];
+    q.k = k[p];
+    q.h0_index = p;
+    q.h1_first = h1;
+    h1 += k[p];
+    const size_t m = (size_t)q.np * q.ld;
+    f32 += m * (2 + 2 * q.k);
+    u16 += (size_t)q.np * q.np * 2 * (1 + q.k);
+    const int64_t vec = m / 4;
+    const int nch = (int)((vec + kChunkVec - 1) / kChunkVec);
+    q.u0_first = (int)b->c0.size();
+    q.u0_count = nch;
+    for (int c = 0; c < nch; ++c)
+      b->c0.push_back(Chunk{p, -1, (int64_t)c * kChunkVec, std::min<int64_t>(vec, (int64_t)(c + 1) * kChunkVec)});
+    for (int j = 0; j < q.k; ++j) {
+      q.u1_first[j] = (int)b->c1.size();
+      q.u1_count[j] = nch;
+      for (int c = 0; c < nch; ++c)
+        b->c1.push_back(Chunk{p, j, (int64_t)c * kChunkVec, std::min<int64_t>(vec, (int64_t)(c + 1) * kChunkVec)});
+    }
+  }
+  b->total_k = h1;
+  hipError_t e = hipSuccess;
+  float* fbase = nullptr;
+  uint16_t* hbase = nullptr;
+  LayerState* sbase = nullptr;
+  auto get = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = balloc(b, ptr, bytes);
+  };
+  get((void**)&fbase, f32 * 4);
+  get((void**)&hbase, u16 * 2);
+  get((void**)&sbase, sizeof(LayerState) * count);
+  get((void**)&b->dp, sizeof(BatchProblem) * count);
+  get((void**)&b->dc0, sizeof(Chunk) * b->c0.size());
+  get((void**)&b->dc1, sizeof(Chunk) * std::max<size_t>(1, b->c1.size()));
+  get((void**)&b->part0, sizeof(double) * b->c0.size());
+  get((void**)&b->part1f, sizeof(double) * std::max<size_t>(1, b->c1.size()));
+  get((void**)&b->part1m, sizeof(double) * std::max<size_t>(1, b->c1.size()));
+  get((void**)&b->desc[0], sizeof(ProblemDesc) * count);
+  get((void**)&b->desc[1], sizeof(ProblemDesc) * count);
+  size_t n_big = 0, n_small = 0;
+  for (auto& q : b->hp) {
+    const int Tb = (int)((q.n + 255) / 256), Ts = (int)((q.n + 127) / 128);
+    n_big += (size_t)(1 + q.k) * Tb * (Tb + 1) / 2;
+    n_small += (size_t)(1 + q.k) * Ts * (Ts + 1) / 2;
+  }
+  get((void**)&b->items[0], sizeof(TileItem) * n_big);
+  get((void**)&b->items[1], sizeof(TileItem) * n_small);
+  get((void**)&b->h0tab, sizeof(void*) * count);
+  get((void**)&b->p0tab, sizeof(void*) * count);
+  get((void**)&b->h1tab, sizeof(void*) * h1);
+  get((void**)&b->p1tab, sizeof(void*) * h1);
+  get((void**)&b->dsum, sizeof(ProblemSummary) * count);
+  if (e != hipSuccess)
+    return bail(e == hipErrorOutOfMemory ? DMPT_ENOMEM : DMPT_EHIP, "device allocation failed");
+  if (hipHostMalloc((void**)&b->host_tab, sizeof(void*) * 2 * (count + h1), 0) != hipSuccess ||
+      hipHostMalloc((void**)&b->hsum, sizeof(ProblemSummary) * count, 0) != hipSuccess)
+    return bail(DMPT_ENOMEM, "pinned allocation failed");
+  // carve the per-problem buffers (every block a multiple of 256 bytes)
+  size_t fo = 0, ho = 0;
+  for (int p = 0; p < count; ++p) {
+    BatchProblem& q = b->hp[p];
+    const size_t m = (size_t)q.np * q.ld, pm = (size_t)q.np * q.np;
+    q.st = sbase + p;
+    q.s_master = fbase + fo; fo += m;
+    q.x = fbase + fo; fo += m;
+    for (int j = 0; j < q.k; ++j) {
+      q.s1buf[j][0] = fbase + fo; fo += m;
+      q.s1buf[j][1] = fbase + fo; fo += m;
+    }
+    q.s_hi = hbase + ho; ho += pm;
+    q.s_lo = hbase + ho; ho += pm;
+    for (int j = 0; j < q.k; ++j) {
+      q.s1_hi[j] = hbase + ho; ho += pm;
+      q.s1_lo[j] = hbase + ho; ho += pm;
+    }
+  }
+  // the products never write outside each problem's k extent: start from zero
+  if (hipMemset(fbase, 0, f32 * 4) != hipSuccess || hipMemset(hbase, 0, u16 * 2) != hipSuccess ||
+      hipMemset(sbase, 0, sizeof(LayerState) * count) != hipSuccess ||
+      hipMemcpy(b->dp, b->hp.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->dc0, b->c0.data(), sizeof(Chunk) * b->c0.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      (!b->c1.empty() && hipMemcpy(b->dc1, b->c1.data(), sizeof(Chunk) * b->c1.size(),
+                                   hipMemcpyHostToDevice) != hipSuccess))
+    return bail(DMPT_EHIP, "workspace set-up failed");
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
+    return bail(DMPT_EHIP, "stream/event creation failed");
+  if (autotune(b) != hipSuccess) return bail(DMPT_EHIP, "tile autotuning failed");
+  *out = b;
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_batch_response(dmpt_batch* b, const double* const* H0, const double* const* H1,
+                                double* const* P0, double* const* P1, dmpt_problem_stats* st,
+                                double* ms) {
+  if (!b || !H0 || !H1 || !P1) return bfail(DMPT_EINVAL, "NULL argument");
+  const int P = b->count, K = b->total_k;
+  void** h = b->host_tab;
+  for (int p = 0; p < P; ++p) {
+    h[p] = (void*)H0[p];
+    h[P + p] = P0 ? (void*)P0[p] : nullptr;
+    if (!H0[p]) return bfail(DMPT_EINVAL, "NULL H0[p]");
+  }
+  for (int i = 0; i < K; ++i) {
+    h[2 * P + i] = (void*)H1[i];
+    h[2 * P + K + i] = (void*)P1[i];
+    if (!H1[i] || !P1[i]) return bfail(DMPT_EINVAL, "NULL H1 or P1 entry");
+  }
+  hipStream_t s = b->stream;
+  BCHK(hipMemcpyAsync(b->h0tab, h, sizeof(void*) * P, hipMemcpyHostToDevice, s));
+  BCHK(hipMemcpyAsync(b->p0tab, h + P, sizeof(void*) * P, hipMemcpyHostToDevice, s));
+  BCHK(hipMemcpyAsync(b->h1tab, h + 2 * P, sizeof(void*) * K, hipMemcpyHostToDevice, s));
+  BCHK(hipMemcpyAsync(b->p1tab, h + 2 * P + K, sizeof(void*) * K, hipMemcpyHostToDevice, s));
+  BCHK(hipEventRecord(b->ev0, s));
+  if (b->use_graph) {
+    if (!b->exec) {
+      BCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = enqueue(b, b->cap);
+      hipGraph_t g = nullptr;
+      hipError_t ee = hipStreamEndCapture(b->cap, &g);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return bfail(DMPT_EHIP, std::string("graph capture: ") +
+                                    hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
+      b->graph = g;
+      BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    BCHK(hipGraphLaunch(b->exec, s));
+  } else {
+    BCHK(enqueue(b, s));
+  }
+  BCHK(hipEventRecord(b->ev1, s));
+  BCHK(hipMemcpyAsync(b->hsum, b->dsum, sizeof(ProblemSummary) * P, hipMemcpyDeviceToHost, s));
+  BCHK(hipStreamSynchronize(s));
+  float t_ms = 0.f;
+  hipEventElapsedTime(&t_ms, b->ev0, b->ev1);
+  if (ms) *ms = t_ms;
+  int err = 0, noconv = 0;
+  for (int p = 0; p < P; ++p) {
+    const ProblemSummary& q = b->hsum[p];
+    if (q.error) err = q.error;
+    if (!q.converged) noconv = 1;
+    if (st) {
+      st[p].layers = q.layers;
+      st[p].d0_layer = q.d0_layer;
+      st[p].converged = q.converged;
+      st[p].k = b->hp[p].k;
+      for (int j = 0; j < kMaxKB; ++j) st[p].d1_layer[j] = q.d1_layer[j];
+      st[p].idem0 = q.idem0;
+      for (int j = 0; j < kMaxKB; ++j) st[p].idem1[j] = q.idem1[j];
+    }
+  }
+  if (err) return bfail((dmpt_status)err, "non-finite value or split overflow in a problem");
+  if (noconv) return bfail(DMPT_ENOCONV, "layer cap reached before every D1 test fired");
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_batch_info(const dmpt_batch* b, int32_t* threshold, int32_t* n_items_256,
+                            int32_t* n_items_128) {
+  if (!b) return bfail(DMPT_EINVAL, "NULL batch");
+  if (threshold) *threshold = b->threshold;
+  if (n_items_256) *n_items_256 = b->n_items[0];
+  if (n_items_128) *n_items_128 = b->n_items[1];
+  return DMPT_OK;
+}
+
+void dmpt_batch_destroy(dmpt_batch* b) { batch_free(b); }
+
+}  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "dmpt.h"
 
 namespace dmpt {
@@ -80,8 +82,24 @@ struct LayerState {
 // One output tile of a layer product.  out = 0: X = S^2; out = 1 + j: X1_j.
 struct TileItem {
   int16_t out;
-  int16_t pad;
+  int16_t prob;              // problem index (batched launches; 0 otherwise)
   int32_t ti, tj;            // tile row/col (ti <= tj)
+};
+
+constexpr int kMaxKB = 3;    // most responses per problem of a batch
+
+// Operands of one problem in a batched product launch.
+struct ProblemDesc {
+  const void* s_hi;
+  const void* s_lo;
+  const void* s1_hi[kMaxKB];
+  const void* s1_lo[kMaxKB];
+  void* x;
+  void* x1[kMaxKB];
+  const LayerState* state;
+  int64_t ld;                // row stride of X and X1
+  int64_t kdim;              // k extent of the products (multiple of the tile)
+  int64_t pdim;              // panel-layout size of the 16-bit operands (multiple of 256)
 };
 
 // Pointers of the layer products.  The product kernels read `state` to skip
@@ -94,6 +112,7 @@ struct ProductArgs {
   void* x;                   // X (FP32 or FP64)
   void* x1[kMaxK];           // X1_j
   const void* a_op[kMaxK];    // direct forms: A operand of output 1 + j (NULL: S)
+  const ProblemDesc* probs;  // split forms, batched: per-item operands (NULL: the fields here)
   const TileItem* items;
   const LayerState* state;   // NULL: compute every item, scales taken from s1_exp
   int32_t s1_exp[kMaxK];     // used when state == NULL
@@ -107,6 +126,9 @@ struct ProductArgs {
 // layer products (kernels_gemm.hip)
 int product_tile(dmpt_precision prec);   // output tile edge used by the product kernels
 hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s);
+// batched split products with 256- or 128-row tiles (a.probs set)
+hipError_t launch_products_batch(dmpt_precision prec, int tile, const ProductArgs& a,
+                                 hipStream_t s);
 
 // layer kernels (kernels_layer.hip)
 hipError_t launch_gershgorin(const double* H, int64_t n, double* partial /* 3*512 */,
@@ -153,5 +175,8 @@ hipError_t launch_adj_update(dmpt_precision prec, const LayerState* fwd, int lay
 hipError_t launch_adj_out(dmpt_precision prec, const LayerState* fwd, const void* src, int64_t ld,
                           double* dst, int64_t n, hipStream_t s);
 hipError_t launch_selftest_mfma(int32_t* result, hipStream_t s);
+
+// Record the reason of a non-OK status for dmpt_last_error (dmpt_api.hip).
+void set_last_error(const char* msg);
 
 }  // namespace dmpt

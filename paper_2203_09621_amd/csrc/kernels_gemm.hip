@@ -58,7 +58,7 @@ template <> struct Split16<__bf16> {
 // Resolve the skip flags and the operand scale of one tile item.
 // Returns false when the item has nothing to do.
 __device__ __forceinline__ bool item_active(const ProductArgs& a, const TileItem& it, int* sexp) {
-  const LayerState* st = a.state;
+  const LayerState* st = a.probs ? a.probs[it.prob].state : a.state;
   if (st) {
     if (st->done) return false;
     if (it.out == 0 ? st->d0 : st->d1[it.out - 1]) return false;
@@ -115,35 +115,39 @@ k_products_split(const ProductArgs a) {
   int sexp = 0;
   if (!item_active(a, it, &sexp)) continue;
 
-  const int64_t ld = a.ld;
   const int j = it.out - 1;
   const int nprod = it.out == 0 ? 1 : 2;
+  // operands of this item: the batch descriptor or the single-problem fields
+  const ProblemDesc* pd = a.probs ? a.probs + it.prob : nullptr;
+  const int64_t ld = pd ? pd->ld : a.ld;
+  const int64_t kdim = pd ? pd->kdim : a.kdim;
+  const int64_t pdim = pd ? pd->pdim : a.kdim;
   // operand panels per product: [hi_A, lo_A, hi_B, lo_B]
   const uint16_t* P[2][4];
   {
-    const uint16_t* sh = (const uint16_t*)a.s_hi;
-    const uint16_t* sl = (const uint16_t*)a.s_lo;
+    const uint16_t* sh = (const uint16_t*)(pd ? pd->s_hi : a.s_hi);
+    const uint16_t* sl = (const uint16_t*)(pd ? pd->s_lo : a.s_lo);
     if (it.out == 0) {
       P[0][0] = sh; P[0][1] = sl; P[0][2] = sh; P[0][3] = sl;
       P[1][0] = sh; P[1][1] = sl; P[1][2] = sh; P[1][3] = sl;
     } else {
-      const uint16_t* th = (const uint16_t*)a.s1_hi[j];
-      const uint16_t* tl = (const uint16_t*)a.s1_lo[j];
+      const uint16_t* th = (const uint16_t*)(pd ? pd->s1_hi[j] : a.s1_hi[j]);
+      const uint16_t* tl = (const uint16_t*)(pd ? pd->s1_lo[j] : a.s1_lo[j]);
       P[0][0] = sh; P[0][1] = sl; P[0][2] = th; P[0][3] = tl;
       P[1][0] = th; P[1][1] = tl; P[1][2] = sh; P[1][3] = sl;
     }
   }
   const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BN;
-  const int kt_per = (int)(a.kdim / BK);
+  const int kt_per = (int)(kdim / BK);
   const int ktiles = nprod * kt_per;
 
   // Operands are panel-major: the k-tile kt of row tile I is the contiguous
   // block (I * kblocks + kt) of kPanelRows x kPanelK elements.  Per-thread
   // offset inside a block; the swizzle of row i*RPL + lrow does not depend on
   // i, so every load round adds only a wave-uniform offset.
-  static_assert(BM == kPanelRows && BK == kPanelK, "tile = panel block");
+  static_assert(kPanelRows % BM == 0 && BK == kPanelK, "tile inside a panel block");
   static_assert((RPL >> SWZ) % CH == 0, "swizzle must repeat every load round");
-  const int64_t kblocks = a.kdim / kPanelK;
+  const int64_t kblocks = pdim / kPanelK;
   const int csrc = lsl ^ ((lrow >> SWZ) & (CH - 1));
   const int voff = lrow * kPanelK + csrc * 8;
   auto issue = [&](int t) {
@@ -153,9 +157,9 @@ k_products_split(const ProductArgs a) {
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int arr = (i * RPL) / BM;             // compile-time after unrolling
-      const int64_t tile = arr < 2 ? it.ti : it.tj;
-      const int64_t soff = (tile * kblocks + kt) * (kPanelRows * kPanelK) +
-                           (int64_t)(i * RPL - arr * BM) * kPanelK;   // wave-uniform
+      const int64_t row0 = arr < 2 ? row_a0 : row_b0;
+      const int64_t soff = ((row0 / kPanelRows) * kblocks + kt) * (kPanelRows * kPanelK) +
+                           (row0 % kPanelRows + (int64_t)(i * RPL - arr * BM)) * kPanelK;
       const uint16_t* basep = (p == 0 ? P[0][arr] : P[1][arr]) + soff;
       u32x4* dst = dst_stage + (i * RPL + wave * RPW) * CH;            // wave-uniform
       __builtin_amdgcn_global_load_lds((const void*)(basep + voff), (void*)dst, 16, 0, 0);
@@ -229,7 +233,7 @@ k_products_split(const ProductArgs a) {
 
   // epilogue: unscale, store the tile and its mirror image
   const float scale = ldexpf(1.0f, -(S::kShift + sexp));
-  float* C = (float*)(it.out == 0 ? a.x : a.x1[j]);
+  float* C = (float*)(pd ? (it.out == 0 ? pd->x : pd->x1[j]) : (it.out == 0 ? a.x : a.x1[j]));
   const bool diag = it.ti == it.tj;
 #pragma unroll
   for (int m = 0; m < FM; ++m)
@@ -467,6 +471,23 @@ static hipError_t launch_split_cfg(const ProductArgs& a, hipStream_t s) {
 template <typename T16>
 static hipError_t launch_split(const ProductArgs& a, hipStream_t s) {
   return launch_split_cfg<T16, kPanelK, kSplitWGM, kSplitWGN, 2, 2>(a, s);
+}
+
+template <typename T16>
+static hipError_t launch_split_small(const ProductArgs& a, hipStream_t s) {
+  // 128 x 128 tiles, 4 waves of 64 x 64, two workgroups per CU
+  constexpr size_t lds = (size_t)2 * (4 * 128) * (kPanelK / 8) * 16;
+  return launch_one(k_products_split<T16, 128, kPanelK, 2, 2, 2, 2>, 4 * kWave, lds, 2, a, s);
+}
+
+hipError_t launch_products_batch(dmpt_precision prec, int tile, const ProductArgs& a,
+                                 hipStream_t s) {
+  if (!a.probs) return hipErrorInvalidValue;
+  if (prec == DMPT_SPLIT_FP16)
+    return tile == 128 ? launch_split_small<_Float16>(a, s) : launch_split<_Float16>(a, s);
+  if (prec == DMPT_SPLIT_BF16)
+    return tile == 128 ? launch_split_small<__bf16>(a, s) : launch_split<__bf16>(a, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s) {

@@ -6,92 +6,9 @@
 // point atomics.
 #include <math.h>
 
-#include "dmpt_internal.h"
+#include "layer_common.h"
 
 namespace dmpt {
-
-constexpr int kBlk = 256;
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
-}
-
-// Block-wide reductions for kBlk threads; the result is valid in every thread.
-__device__ double block_sum(double v) {
-  __shared__ double sh[kBlk / kWave];
-  v = wave_sum(v);
-  const int w = threadIdx.x / kWave;
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
-  __syncthreads();
-  double r = 0.0;
-#pragma unroll
-  for (int i = 0; i < kBlk / kWave; ++i) r += sh[i];
-  return r;
-}
-__device__ double block_max(double v) {
-  __shared__ double sh[kBlk / kWave];
-  v = wave_max(v);
-  const int w = threadIdx.x / kWave;
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
-  __syncthreads();
-  double r = sh[0];
-#pragma unroll
-  for (int i = 1; i < kBlk / kWave; ++i) r = fmax(r, sh[i]);
-  return r;
-}
-__device__ double block_min(double v) {
-  __shared__ double sh[kBlk / kWave];
-  v = wave_min(v);
-  const int w = threadIdx.x / kWave;
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
-  __syncthreads();
-  double r = sh[0];
-#pragma unroll
-  for (int i = 1; i < kBlk / kWave; ++i) r = fmin(r, sh[i]);
-  return r;
-}
-
-// Split scale: choose e with max|Y| 2^e in [1/16, 1/8), leaving room for the
-// growth of one layer before the next choice.
-__device__ __forceinline__ int split_exponent(double m) {
-  if (!(m > 0.0) || !isfinite(m)) return 0;
-  return -ilogb(m) - 4;
-}
-
-template <typename T16> struct Conv;
-template <> struct Conv<_Float16> {
-  static __device__ __forceinline__ uint16_t to(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
-  static __device__ __forceinline__ float from(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
-};
-template <> struct Conv<__bf16> {
-  static __device__ __forceinline__ uint16_t to(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
-  static __device__ __forceinline__ float from(uint16_t b) { return (float)__builtin_bit_cast(__bf16, b); }
-};
-
-// hi = RN16(v 2^e), lo = RN16((v 2^e - hi) 2^t); the difference is exact.
-template <typename T16>
-__device__ __forceinline__ void split_one(float v, int e, int t, uint16_t* hi, uint16_t* lo) {
-  const float xs = ldexpf(v, e);
-  const uint16_t h = Conv<T16>::to(xs);
-  *hi = h;
-  *lo = Conv<T16>::to(ldexpf(xs - Conv<T16>::from(h), t));
-}
 
 // ------------------------------------------------------------------ Gershgorin
 // One wave per row: r_i = sum_{j != i} |H_ij|, lo_i = H_ii - r_i, hi_i = H_ii + r_i.
@@ -375,54 +292,7 @@ hipError_t launch_reset_state(LayerState* st, int k, int max_layers, double nocc
 // the D0 test and the N_S update.  After D0 converged: sigma flips.
 template <typename M>
 __global__ void __launch_bounds__(kBlk) k_decide0(LayerState* st, const M* x, int64_t ld) {
-  const int done = st->done;
-  if (done) return;
-  const int d0 = st->d0;
-  const int n_real = st->n_real;
-  double nx = 0.0;
-  if (!d0) {
-    for (int i = threadIdx.x; i < n_real; i += kBlk) nx += (double)x[(int64_t)i * ld + i];
-    nx = block_sum(nx);
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  const int n = st->n + 1;
-  st->n = n;
-  int sig;
-  if (!d0) {
-    st->x_computed = 1;
-    if (!isfinite(nx)) {
-      st->error = DMPT_ENONFINITE;
-      st->done = 1;
-      return;
-    }
-    const double ns = st->n_s, nocc = st->nocc;
-    const double iderr = ns - nx;
-    const double a = fabs(2.0 * ns - nx - nocc), b = fabs(nx - nocc);
-    sig = a > b ? 1 : -1;
-    st->iderr[n] = iderr;
-    const bool conv = iderr <= 0.0 ||
-                      (n > 2 && st->sigma[n - 1] != st->sigma[n - 2] &&
-                       iderr > 4.5 * st->iderr[n - 2] * st->iderr[n - 2]);
-    if (conv) {
-      st->d0 = 1;
-      st->d0_layer = n;
-      st->d0_now = 1;
-      st->upd_s0 = 0;
-      if (n > 1) sig = -st->sigma[n - 1];
-    } else {
-      st->d0_now = 0;
-      st->upd_s0 = 1;
-      st->n_s = sig * nx + (1 - sig) * ns;
-    }
-  } else {
-    st->x_computed = 0;
-    st->upd_s0 = 0;
-    st->d0_now = 0;
-    sig = -st->sigma[n - 1];
-  }
-  st->sigma[n] = sig;
-  st->sigma_cur = sig;
+  decide0_body<M>(st, x, ld);
 }
 
 hipError_t launch_decide0(dmpt_precision prec, LayerState* st, const void* x, int64_t ld,
@@ -445,61 +315,10 @@ __global__ void __launch_bounds__(kBlk) k_update(const LayerState* st, int which
                                                 const M* s_old, M* dst, uint16_t* hi,
                                                 uint16_t* lo, int64_t total, int64_t ld,
                                                 int64_t kdim, int t, double* pfro, double* pmax) {
-  if (st->done) return;
-  const int sig = st->sigma_cur;
-  bool active, want_fro;
-  int e = 0;
-  if (which < 0) {
-    active = st->upd_s0;
-    want_fro = st->x_computed;
-  } else {
-    active = !st->d1[which];
-    want_fro = active && st->d0;
-    e = st->s1_exp_next[which];
-  }
-  if (!active && !want_fro) return;
-  double fro = 0.0, mx = 0.0;
-  typedef M V4 __attribute__((ext_vector_type(4)));
-  const int64_t n4 = total / 4;
-  for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < n4;
-       q += (int64_t)gridDim.x * kBlk) {
-    const V4 xv = ((const V4*)x)[q];
-    const V4 sv = ((const V4*)s_old)[q];
-    if (want_fro) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double d = (double)sv[r] - (double)xv[r];
-        fro += d * d;
-      }
-    }
-    if (active) {
-      V4 nv;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) nv[r] = sig > 0 ? xv[r] : (M)2 * sv[r] - xv[r];
-      ((V4*)dst)[q] = nv;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) mx = fmax(mx, fabs((double)nv[r]));
-      if constexpr (SPLIT) {
-        // four consecutive columns of one row (ld % 4 == 0) stay inside one panel block
-        const int64_t row = (4 * q) / ld, col = 4 * q - row * ld;
-        if (col < kdim) {
-          uint16_t h[4], l[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) split_one<T16>((float)nv[r], e, t, h + r, l + r);
-          typedef uint16_t U4 __attribute__((ext_vector_type(4)));
-          const int64_t pi = panel_index(row, col, kdim) / 4;
-          ((U4*)hi)[pi] = U4{h[0], h[1], h[2], h[3]};
-          ((U4*)lo)[pi] = U4{l[0], l[1], l[2], l[3]};
-        }
-      }
-    }
-  }
-  fro = block_sum(fro);
-  mx = block_max(mx);
-  if (threadIdx.x == 0) {
-    pfro[blockIdx.x] = fro;
-    if (pmax) pmax[blockIdx.x] = mx;
-  }
+  update_body<M, T16, SPLIT>(st, which, x, s_old, dst, hi, lo,
+                             (int64_t)blockIdx.x * kBlk + threadIdx.x, total / 4,
+                             (int64_t)gridDim.x * kBlk, ld, kdim, t, pfro + blockIdx.x,
+                             pmax ? pmax + blockIdx.x : nullptr);
 }
 
 hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, const void* x,
@@ -538,70 +357,15 @@ hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, c
 __global__ void __launch_bounds__(kBlk) k_decide1(LayerState* st, const double* pfro0,
                                                  const double* pfro1, const double* pmax1,
                                                  int split, int lo_shift) {
-  if (st->done) return;
-  const int k = st->k;
-  const int d0_now = st->d0_now, d0 = st->d0;
-  __shared__ double res[2 * kMaxK + 1];
-  // sums in a fixed order: each thread a fixed strided subset, then the block tree
-  if (d0_now) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += kBlk) v += pfro0[i];
-    v = block_sum(v);
-    if (threadIdx.x == 0) res[2 * kMaxK] = v;
+  Partials pr;
+  pr.fro0 = pfro0;
+  pr.n0 = kRedBlocks;
+  for (int j = 0; j < kMaxK; ++j) {
+    pr.fro1[j] = pfro1 + (size_t)j * kRedBlocks;
+    pr.max1[j] = pmax1 + (size_t)j * kRedBlocks;
+    pr.n1[j] = kRedBlocks;
   }
-  for (int j = 0; j < k; ++j) {
-    if (st->d1[j]) continue;
-    double v = 0.0, m = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += kBlk) {
-      if (d0) v += pfro1[j * kRedBlocks + i];
-      m = fmax(m, pmax1[j * kRedBlocks + i]);
-    }
-    v = block_sum(v);
-    m = block_max(m);
-    if (threadIdx.x == 0) {
-      res[2 * j] = v;
-      res[2 * j + 1] = m;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  const int n = st->n;
-  if (d0_now) {
-    st->fro0 = sqrt(res[2 * kMaxK]);
-    if (!isfinite(st->fro0)) st->error = DMPT_ENONFINITE;
-  }
-  int all = 1;
-  for (int j = 0; j < k; ++j) {
-    if (st->d1[j]) continue;
-    const double mx = res[2 * j + 1];
-    // the split written this layer used s1_exp_next; check it stayed in range
-    if (split && ldexp(mx, st->s1_exp_next[j] + lo_shift) > 32768.0) st->error = DMPT_ENONFINITE;
-    if (!isfinite(mx)) st->error = DMPT_ENONFINITE;
-    if (d0) {
-      const double f = sqrt(res[2 * j]);
-      st->fro1[j][n] = f;
-      if (!isfinite(f)) st->error = DMPT_ENONFINITE;
-      if (n - 2 >= st->d0_layer) {
-        const double prev = st->fro1[j][n - 2];
-        if (f > 9.0 * st->fro0 * prev || f == 0.0) {
-          st->d1[j] = 1;
-          st->d1_layer[j] = n;
-        }
-      }
-    }
-    st->s1_exp_hist[j][n] = st->s1_exp_next[j];   // the scale S1_n was just split with
-    st->s1_exp_split[j] = st->s1_exp_next[j];
-    st->s1_exp_next[j] = split_exponent(mx);
-    st->s1_max[j] = mx;
-    if (!st->d1[j]) all = 0;
-  }
-  if (all) {
-    st->converged = 1;
-    st->done = 1;
-  } else if (n >= st->max_layers) {
-    st->done = 1;
-  }
-  if (st->error) st->done = 1;
+  decide1_body(st, pr, split, lo_shift);
 }
 
 hipError_t launch_decide1(LayerState* st, const double* pfro0, const double* pfro1,

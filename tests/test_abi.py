@@ -36,6 +36,7 @@ def test_status_strings_and_defaults_without_gpu():
 
 def test_struct_sizes_match_c_layout():
     from paper_2203_09621_amd import _native
-    assert ctypes.sizeof(_native.DmptOptions) == 24
+    assert ctypes.sizeof(_native.DmptOptions) == 28
+    assert ctypes.sizeof(_native.DmptProblemStats) == 8 * 4 + 8 * 4
     # 4+4+32+4+4+256 = 304, then 4 + 8 + 1 + 8 + 1 + 1 doubles, then 2 int32
     assert ctypes.sizeof(_native.DmptStats) == 304 + 8 * 23 + 8

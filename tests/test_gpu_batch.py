@@ -1,0 +1,111 @@
+"""Batched solves: every problem of a batch against the FP64 oracle, against
+the same problem solved alone, and graph replays against eager execution."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_2203_09621_amd as dm
+    return dm
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _run(dm, probs, precision="split_bf16", graph=True, reps=1, max_layers=100):
+    b = dm.dmpt_batch_init([p.N for p in probs], [p.nocc for p in probs], [p.k for p in probs],
+                           precision=precision, graph=graph, max_layers=max_layers)
+    try:
+        H0 = [_cuda(p.H0) for p in probs]
+        H1 = [[_cuda(h) for h in p.H1] for p in probs]
+        outs = []
+        for _ in range(reps):
+            P0, P1, st, ms = dm.dmpt_batch_response(b, H0, H1)
+            outs.append(([x.cpu().numpy() for x in P0], [[x.cpu().numpy() for x in ps] for ps in P1],
+                         st, ms))
+        info = dm.dmpt_batch_info(b)
+    finally:
+        dm.dmpt_batch_destroy(b)
+    return outs, info
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    from workloads import config4
+    return config4(count=24, nmax=640)
+
+
+def test_batch_matches_oracle(dm, small_batch):
+    from oracle import exact
+    (res,), info = _run(dm, small_batch)
+    P0, P1, st, ms = res
+    worst = 0.0
+    for i, p in enumerate(small_batch):
+        r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+        e = max([exact.rel_fro(P0[i], r0)] + [exact.rel_fro(a, b) for a, b in zip(P1[i], r1s)])
+        worst = max(worst, e)
+        assert st[i]["converged"], (i, p.N, st[i])
+        assert e < TOL, (i, p.N, e)
+    print(f"batch of {len(small_batch)}: worst rel err {worst:.2e}, {ms:.1f} ms, "
+          f"tile threshold {info[0]}, items {info[1]}+{info[2]}", flush=True)
+
+
+def test_batch_equals_single_solves(dm, small_batch):
+    (res,), _ = _run(dm, small_batch)
+    P0, P1, st, _ = res
+    for i, p in enumerate(small_batch[:8]):
+        q0, q1s, sst = dm.solve(_cuda(p.H0), [_cuda(h) for h in p.H1], p.nocc,
+                                precision="split_bf16")
+        assert st[i]["layers"] == sst["layers"] and st[i]["d0_layer"] == sst["d0_layer"]
+        assert np.abs(P0[i] - q0.cpu().numpy()).max() <= 1e-6
+        for a, b in zip(P1[i], q1s):
+            assert np.abs(a - b.cpu().numpy()).max() <= 1e-6 * max(1.0, np.abs(a).max())
+
+
+def test_graph_replays_equal_eager(dm, small_batch):
+    import torch
+    probs = small_batch[:10]
+    eager, _ = _run(dm, probs, graph=False)
+    graphed, _ = _run(dm, probs, graph=True, reps=3)
+    for rep in graphed:
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            assert np.array_equal(rep[0][i], eager[0][0][i])
+            for a, b in zip(rep[1][i], eager[0][1][i]):
+                assert np.array_equal(a, b)
+
+
+def test_batch_layer_cap_reports_noconv(dm, small_batch):
+    with pytest.raises(dm.DmptError) as ei:
+        _run(dm, small_batch[:4], max_layers=6)
+    assert ei.value.status == -4
+
+
+def test_batch_full_configuration(dm):
+    """512 problems, N in {64, ..., 1024}, gap U[0.3, 1], 1-3 coordinate
+    perturbations, split BF16, one graph; sampled problems against the oracle."""
+    from oracle import exact
+    from workloads import config4
+    probs = config4()
+    (res,), info = _run(dm, probs, max_layers=80)
+    P0, P1, st, ms = res
+    assert all(s["converged"] for s in st)
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for i in sorted(rng.choice(len(probs), 24, replace=False)):
+        p = probs[i]
+        r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+        e = max([exact.rel_fro(P0[i], r0)] + [exact.rel_fro(a, b) for a, b in zip(P1[i], r1s)])
+        worst = max(worst, e)
+        assert e < TOL, (i, p.N, e)
+    print(f"512 problems: {ms:.1f} ms ({len(probs) / ms * 1e3:.0f} solves/s), worst sampled "
+          f"err {worst:.2e}, threshold {info[0]}", flush=True)

@@ -9,8 +9,11 @@ Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 
-  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--precision P]
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4] [--precision P]
                   [--no-fp64] [--no-cpu] [--no-oracle]
+
+Workload c4 is the batched form: 512 problems of uneven size in one
+graph-captured response per step (split BF16 unless --precision says otherwise).
 """
 from __future__ import annotations
 
@@ -130,13 +133,106 @@ def cpu_baseline(p, workload, layers):
             "seconds_full_estimate": t_full}
 
 
+def batch_main(args, torch, dm):
+    """Batched workload: one step = dmpt_batch_response over the 512 problems."""
+    from workloads import config4
+    if not args.precision.startswith("split"):
+        raise SystemExit("the batched form runs the split precisions only")
+    prec = args.precision
+    t = time.perf_counter()
+    probs = config4()
+    log(f"workload batch: {len(probs)} problems, N {min(p.N for p in probs)}..{max(p.N for p in probs)}"
+        f"  ({time.perf_counter() - t:.1f} s)")
+    dev = torch.device("cuda:0")
+    H0 = [torch.from_numpy(p.H0).to(dev) for p in probs]
+    H1 = [[torch.from_numpy(h).to(dev) for h in p.H1] for p in probs]
+    P0 = [torch.empty_like(h) for h in H0]
+    P1 = [[torch.empty_like(h) for h in hs] for hs in H1]
+    t = time.perf_counter()
+    b = dm.dmpt_batch_init([p.N for p in probs], [p.nocc for p in probs], [p.k for p in probs],
+                           precision=prec, max_layers=args.batch_layers, graph=True)
+    th, n256, n128 = dm.dmpt_batch_info(b)
+    log(f"batch init + tile tuning: {time.perf_counter() - t:.1f} s; threshold {th}, "
+        f"items {n256} (256) + {n128} (128)")
+    for w in range(args.warmup):
+        _, _, st, dms = dm.dmpt_batch_response(b, H0, H1, P0, P1)
+        log(f"warmup {w}: {dms:.1f} ms device, max layers {max(s['layers'] for s in st)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev_ms = []
+    for _ in range(args.steps):
+        _, _, st, dms = dm.dmpt_batch_response(b, H0, H1, P0, P1)
+        dev_ms.append(dms)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms:.2f} ms/step ({np.mean(dev_ms):.2f} ms device)")
+    value = sum(5.0 * p.N ** 3 * s["layers"] for p, s in zip(probs, st)) / (ms * 1e-3) / 1e12
+    alg = 0.0
+    for p, s in zip(probs, st):
+        ends = [d if d > 0 else s["layers"] for d in s["d1_layer"]]
+        ka = [sum(1 for e in ends if layer <= e) for layer in range(1, s["layers"] + 1)]
+        alg += algorithmic_flops(p.N, ka, s["d0_layer"] or s["layers"], prec)
+    achieved = alg / (ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    out = {
+        "metric": METRIC, "value": round(value, 3),
+        "unit": "TFLOP/s (paper convention: 5 N^3 per layer, FMA = 1, summed over problems)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"split_fp16": "f16", "split_bf16": "bf16"}[prec], "data": "synthetic",
+        "config": {"workload": "batch512_N64-1024", "problems": len(probs),
+                   "precision": prec, "accumulate": "f32", "tile_threshold": th,
+                   "max_layers": max(s["layers"] for s in st),
+                   "graph_layers": args.batch_layers},
+        "solves_per_s": round(len(probs) / (ms * 1e-3), 1),
+        "time_to_p1_ms": round(ms, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "whole batched response (algorithmic product FLOPs / step time)"},
+    }
+    if not (args.no_oracle and args.no_cpu):
+        # one pass of the FP64 oracle over the whole batch gives both the
+        # errors and the host-core baseline (about 30 s of CPU work)
+        from oracle import exact
+        cores = os.cpu_count()
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+        except Exception:  # pragma: no cover
+            pass
+        P0h = [x.cpu().numpy() for x in P0]
+        P1h = [[x.cpu().numpy() for x in xs] for xs in P1]
+        errs = []
+        t_or = 0.0
+        for i, p in enumerate(probs):
+            t = time.perf_counter()
+            r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+            t_or += time.perf_counter() - t
+            errs.append(max([exact.rel_fro(P0h[i], r0)] +
+                            [exact.rel_fro(P1h[i][j], r) for j, r in enumerate(r1s)]))
+        log(f"oracle over all problems: {t_or:.1f} s, max err {max(errs):.2e}")
+        if not args.no_oracle:
+            out["rel_fro_err"] = {"max": max(errs), "median": float(np.median(errs)),
+                                  "p99": float(np.quantile(errs, 0.99))}
+        if not args.no_cpu:
+            out["cpu_baseline"] = {
+                "value": round(value * (ms * 1e-3) / t_or, 4), "unit": out["unit"],
+                "cores": cores, "kind": "oracle", "solves_per_s": round(len(probs) / t_or, 2),
+                "sample": f"exact FP64 oracle (LAPACK eigh + sum-over-states) over all "
+                          f"{len(probs)} problems of the batch: {t_or:.1f} s"}
+    dm.dmpt_batch_destroy(b)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1"])
-    ap.add_argument("--precision", default="split_fp16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4"])
+    ap.add_argument("--precision", default=None, choices=list(PEAK_TFLOPS))
+    ap.add_argument("--batch-layers", type=int, default=100,
+                    help="layers captured in the batched graph (c4)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-oracle", action="store_true", help="skip the error vs the oracle")
@@ -149,6 +245,13 @@ def main():
     import torch
     import paper_2203_09621_amd as dm
 
+    args.precision_given = args.precision is not None
+    if args.workload == "c4":
+        if args.precision is None:
+            args.precision = "split_bf16"
+        return batch_main(args, torch, dm)
+    if args.precision is None:
+        args.precision = "split_fp16"
     t = time.perf_counter()
     p = make_workload(args.workload)
     log(f"workload {p.name}: N={p.N} nocc={p.nocc} k={p.k}  ({time.perf_counter() - t:.1f} s)")

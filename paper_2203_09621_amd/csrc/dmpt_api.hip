@@ -115,12 +115,18 @@ struct dmpt_ctx {
   LayerState* st;
   void* s_init;
   void* s_master;
-  void* s_hi;
-  void* s_lo;
-  void* x;
+  void* s_hi[2];      // split forms: 16-bit split of S (two buffers, see ProblemDesc)
+  void* s_lo[2];
+  void* x;            // X = S^2 (direct forms and the adjoint's recomputation)
   void* s1buf[kMaxK][2];
-  void* s1_hi[kMaxK];
-  void* s1_lo[kMaxK];
+  void* s1_hi[kMaxK][2];
+  void* s1_lo[kMaxK][2];
+  ProblemDesc* desc;  // split forms: buffers of the fused layer (device)
+  double* part_f;     // split forms: per-item partials of the fused layer
+  double* part_m;
+  TraceBlock* tblocks;// split forms: diagonal blocks of Tr X
+  int n_tblocks;
+  double* part_tr;
   double* part;       // reduction partials
   double* dscal;      // device scalars (traces)
   int32_t* dflag;
@@ -273,24 +279,27 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
   get((void**)&c->st, sizeof(LayerState));
   get(&c->s_init, mat * eb);
   get(&c->s_master, mat * eb);
-  get(&c->x, mat * eb);
+  const bool split = is_split(c->prec);
+  c->ckpt = opt.ckpt_every > 0 ? opt.ckpt_every : 0;
+  if (!split || c->ckpt) get(&c->x, mat * eb);
   const size_t pmat = (size_t)c->np * c->np;   // panel-major 16-bit operands
-  if (is_split(c->prec)) {
-    get(&c->s_hi, pmat * 2);
-    get(&c->s_lo, pmat * 2);
-  }
+  if (split)
+    for (int b = 0; b < 2; ++b) {
+      get(&c->s_hi[b], pmat * 2);
+      get(&c->s_lo[b], pmat * 2);
+    }
   for (int j = 0; j < k_max; ++j) {
     get(&c->s1buf[j][0], mat * eb);
     get(&c->s1buf[j][1], mat * eb);
-    if (is_split(c->prec)) {
-      get(&c->s1_hi[j], pmat * 2);
-      get(&c->s1_lo[j], pmat * 2);
-    }
+    if (split)
+      for (int b = 0; b < 2; ++b) {
+        get(&c->s1_hi[j][b], pmat * 2);
+        get(&c->s1_lo[j][b], pmat * 2);
+      }
   }
   get((void**)&c->part, kPartTotal * sizeof(double));
   get((void**)&c->dscal, 16 * sizeof(double));
   get((void**)&c->dflag, 16 * sizeof(int32_t));
-  c->ckpt = opt.ckpt_every > 0 ? opt.ckpt_every : 0;
   if (c->ckpt) {
     // checkpoints of (S, S1_j) at layers 0, c, 2c, ... and one segment of c + 1 layers
     c->nslots = c->max_layers / c->ckpt + 1;
@@ -335,10 +344,42 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
       e = hipMemcpy(c->items[k], items.data(), items.size() * sizeof(TileItem),
                     hipMemcpyHostToDevice);
   }
+  if (split) {
+    get((void**)&c->part_f, (size_t)c->n_items[k_max] * sizeof(double));
+    get((void**)&c->part_m, (size_t)c->n_items[k_max] * sizeof(double));
+    get((void**)&c->desc, sizeof(ProblemDesc));
+    c->n_tblocks = (int)((N + 31) / 32);
+    get((void**)&c->tblocks, (size_t)c->n_tblocks * sizeof(TraceBlock));
+    get((void**)&c->part_tr, (size_t)c->n_tblocks * sizeof(double));
+    if (e == hipSuccess) {
+      std::vector<TraceBlock> tb(c->n_tblocks);
+      for (int b = 0; b < c->n_tblocks; ++b) tb[b] = TraceBlock{0, b};
+      e = hipMemcpy(c->tblocks, tb.data(), tb.size() * sizeof(TraceBlock), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) {
+      ProblemDesc d;
+      memset(&d, 0, sizeof(d));
+      for (int b = 0; b < 2; ++b) {
+        d.s_hi[b] = c->s_hi[b];
+        d.s_lo[b] = c->s_lo[b];
+        for (int j = 0; j < k_max; ++j) {
+          d.s1_hi[j][b] = c->s1_hi[j][b];
+          d.s1_lo[j][b] = c->s1_lo[j][b];
+          d.s1m[j][b] = (float*)c->s1buf[j][b];
+        }
+      }
+      d.s_master = (float*)c->s_master;
+      d.state = c->st;
+      d.ld = c->ld;
+      d.kdim = c->np;
+      d.pdim = c->np;
+      e = hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice);
+    }
+  }
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
     return bail(DMPT_ENOMEM, "device allocation failed");
   // the products never write the pad columns of X and X1: they must start at zero
-  if (e == hipSuccess) e = hipMemset(c->x, 0, mat * eb);
+  if (e == hipSuccess && c->x) e = hipMemset(c->x, 0, mat * eb);
   for (int j = 0; j < k_max && e == hipSuccess; ++j) {
     e = hipMemset(c->s1buf[j][0], 0, mat * eb);
     if (e == hipSuccess) e = hipMemset(c->s1buf[j][1], 0, mat * eb);
@@ -390,10 +431,10 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
 
   HIPCHK(hipEventRecord(c->ev0, s));
   HIPCHK(launch_reset_state(c->st, k, c->max_layers, (double)c->nocc, c->n, s));
-  HIPCHK(launch_load_s0(prec, c->s_init, c->s_master, c->s_hi, c->s_lo, np, ld, t, s));
+  HIPCHK(launch_load_s0(prec, c->s_init, c->s_master, c->s_hi[0], c->s_lo[0], np, ld, t, s));
   for (int j = 0; j < k; ++j)
     HIPCHK(launch_init_s1(prec, H1[j], c->n, np, ld, c->st, j, c->part + kPartMaxabs,
-                          c->s1buf[j][0], c->s1_hi[j], c->s1_lo[j], t, 0.0, s));
+                          c->s1buf[j][0], c->s1_hi[j][0], c->s1_lo[j][0], t, 0.0, s));
 
   const size_t mbytes = (size_t)elems * elem_bytes(prec);
   auto save_ckpt = [&](int layer) -> hipError_t {
@@ -410,39 +451,54 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
 
   ProductArgs pa;
   memset(&pa, 0, sizeof(pa));
-  pa.s_hi = split ? c->s_hi : c->s_master;
-  pa.s_lo = c->s_lo;
-  pa.x = c->x;
   pa.items = c->items[k];
   pa.n_items = c->n_items[k];
-  pa.state = c->st;
-  pa.ld = ld;
-  pa.kdim = np;
   pa.lo_shift = t;
+  if (split) {
+    // fused layer: decisions, then products with the update in their epilogue
+    pa.probs = c->desc;
+    pa.part_f = c->part_f;
+    pa.part_m = c->part_m;
+    pa.slot_base = 0;
+  } else {
+    pa.s_hi = c->s_master;
+    pa.x = c->x;
+    pa.state = c->st;
+    pa.ld = ld;
+    pa.kdim = np;
+  }
 
   int n = 0;
   bool stopped = false;
   while (n < c->max_layers && !stopped) {
     ++n;
     const int cur = n & 1, prv = cur ^ 1;
-    for (int j = 0; j < k; ++j) {
-      pa.s1_hi[j] = split ? c->s1_hi[j] : c->s1buf[j][prv];
-      pa.s1_lo[j] = c->s1_lo[j];
-      pa.x1[j] = c->s1buf[j][cur];
+    if (split) {
+      HIPCHK(launch_trace_diag(prec, c->desc, c->tblocks, c->n_tblocks, c->part_tr, s));
+      HIPCHK(launch_predecide(c->st, c->part_tr, c->n_tblocks, s));
+      if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1)], s));
+      HIPCHK(launch_products_fused(prec, product_tile(prec), pa, s));
+      if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1) + 1], s));
+      HIPCHK(launch_postdecide(c->st, c->items[k], c->n_items[k], c->part_f, c->part_m, t, s));
+    } else {
+      for (int j = 0; j < k; ++j) {
+        pa.s1_hi[j] = c->s1buf[j][prv];
+        pa.x1[j] = c->s1buf[j][cur];
+      }
+      if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1)], s));
+      HIPCHK(launch_products(prec, pa, s));
+      if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1) + 1], s));
+      HIPCHK(launch_decide0(prec, c->st, c->x, ld, s));
+      HIPCHK(launch_update(prec, c->st, -1, c->x, c->s_master, c->s_master, nullptr, nullptr, np,
+                           ld, t, c->part + kPartFro0, nullptr, s));
+      for (int j = 0; j < k; ++j)
+        HIPCHK(launch_update(prec, c->st, j, c->s1buf[j][cur], c->s1buf[j][prv], c->s1buf[j][cur],
+                             nullptr, nullptr, np, ld, t,
+                             c->part + kPartFro1 + (size_t)j * kRedBlocks,
+                             c->part + kPartMax1 + (size_t)j * kRedBlocks, s));
+      HIPCHK(launch_decide1(c->st, c->part + kPartFro0, c->part + kPartFro1, c->part + kPartMax1,
+                            split, t, s));
     }
-    if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1)], s));
-    HIPCHK(launch_products(prec, pa, s));
-    if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1) + 1], s));
-    HIPCHK(launch_decide0(prec, c->st, c->x, ld, s));
-    HIPCHK(launch_update(prec, c->st, -1, c->x, c->s_master, c->s_master, c->s_hi, c->s_lo, np,
-                         ld, t, c->part + kPartFro0, nullptr, s));
-    for (int j = 0; j < k; ++j)
-      HIPCHK(launch_update(prec, c->st, j, c->s1buf[j][cur], c->s1buf[j][prv], c->s1buf[j][cur],
-                           c->s1_hi[j], c->s1_lo[j], np, ld, t,
-                           c->part + kPartFro1 + (size_t)j * kRedBlocks,
-                           c->part + kPartMax1 + (size_t)j * kRedBlocks, s));
-    HIPCHK(launch_decide1(c->st, c->part + kPartFro0, c->part + kPartFro1, c->part + kPartMax1,
-                          split, t, s));
     if (c->ckpt && n % c->ckpt == 0) HIPCHK(save_ckpt(n));
     if (n % c->poll == 0 || n == c->max_layers) {
       HIPCHK(hipMemcpyAsync(c->hflag, &c->st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -526,8 +582,8 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
 
   ProductArgs fa;                     // forward replay (layer precision, replay state)
   memset(&fa, 0, sizeof(fa));
-  fa.s_hi = split ? c->s_hi : c->s_master;
-  fa.s_lo = c->s_lo;
+  fa.s_hi = split ? c->s_hi[0] : c->s_master;
+  fa.s_lo = c->s_lo[0];
   fa.x = c->x;
   fa.items = c->items[k];
   fa.n_items = c->n_items[k];
@@ -555,27 +611,28 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
     if (e - 1 >= b + 1) {
       HIPCHK(hipMemcpyAsync(c->s_master, c->seg_s[0], mbytes, hipMemcpyDeviceToDevice, s));
       if (split)
-        HIPCHK(launch_resplit(prec, c->st, -1, 0, c->s_master, c->s_hi, c->s_lo, np, ld, t, s));
+        HIPCHK(launch_resplit(prec, c->st, -1, 0, c->s_master, c->s_hi[0], c->s_lo[0], np, ld, t,
+                              s));
       for (int j = 0; j < k; ++j) {
         HIPCHK(hipMemcpyAsync(c->s1buf[j][b & 1], c->seg_s1[j], mbytes, hipMemcpyDeviceToDevice, s));
         if (split)
-          HIPCHK(launch_resplit(prec, c->st, j, b, c->s1buf[j][b & 1], c->s1_hi[j], c->s1_lo[j],
-                                np, ld, t, s));
+          HIPCHK(launch_resplit(prec, c->st, j, b, c->s1buf[j][b & 1], c->s1_hi[j][0],
+                                c->s1_lo[j][0], np, ld, t, s));
       }
       for (int n = b + 1; n <= e - 1; ++n) {
         const int cur = n & 1, prv = cur ^ 1;
         HIPCHK(launch_replay_state(c->st, c->st_rep, n, s));
         for (int j = 0; j < k; ++j) {
-          fa.s1_hi[j] = split ? c->s1_hi[j] : c->s1buf[j][prv];
-          fa.s1_lo[j] = c->s1_lo[j];
+          fa.s1_hi[j] = split ? c->s1_hi[j][0] : c->s1buf[j][prv];
+          fa.s1_lo[j] = c->s1_lo[j][0];
           fa.x1[j] = c->s1buf[j][cur];
         }
         HIPCHK(launch_products(prec, fa, s));
-        HIPCHK(launch_update(prec, c->st_rep, -1, c->x, c->s_master, c->s_master, c->s_hi, c->s_lo,
-                             np, ld, t, c->part + kPartFro0, nullptr, s));
+        HIPCHK(launch_update(prec, c->st_rep, -1, c->x, c->s_master, c->s_master, c->s_hi[0],
+                             c->s_lo[0], np, ld, t, c->part + kPartFro0, nullptr, s));
         for (int j = 0; j < k; ++j)
           HIPCHK(launch_update(prec, c->st_rep, j, c->s1buf[j][cur], c->s1buf[j][prv],
-                               c->s1buf[j][cur], c->s1_hi[j], c->s1_lo[j], np, ld, t,
+                               c->s1buf[j][cur], c->s1_hi[j][0], c->s1_lo[j][0], np, ld, t,
                                c->part + kPartFro1 + (size_t)j * kRedBlocks,
                                c->part + kPartMax1 + (size_t)j * kRedBlocks, s));
         HIPCHK(hipMemcpyAsync(c->seg_s[n - b], c->s_master, mbytes, hipMemcpyDeviceToDevice, s));

@@ -1,10 +1,10 @@
 // Batched DNN-SP2-PT: many independent Hamiltonians of different sizes run
-// Algorithms 1-3 together.  All problems advance layer by layer: one
-// persistent product launch per tile class covers the tiles of every problem
-// still running, the decisions run as one workgroup per problem, and the
-// fused updates walk a block table of (problem, matrix, chunk) entries.  Each
-// problem keeps its own LayerState, so problems stop independently; kernels
-// skip problems that are done.  The whole response (normalisation, every
+// Algorithms 1-3 together.  All problems advance layer by layer: the
+// decisions run as one workgroup per problem, and one persistent fused
+// product launch per tile class covers the tiles of every problem still
+// running, with the layer update in its epilogue.  Each problem keeps its own
+// LayerState, so problems stop independently; kernels skip problems that are
+// done.  The whole response (normalisation, every
 // layer up to the cap, outputs) is captured once into a HIP graph and
 // replayed; inputs and outputs reach the graph through device pointer tables.
 #include <stdlib.h>
@@ -21,17 +21,20 @@ namespace dmpt {
 struct BatchProblem {
   LayerState* st;
   float* s_master;
-  uint16_t* s_hi;
-  uint16_t* s_lo;
-  float* x;
+  uint16_t* s_hi[2];
+  uint16_t* s_lo[2];
   float* s1buf[kMaxKB][2];
-  uint16_t* s1_hi[kMaxKB];
-  uint16_t* s1_lo[kMaxKB];
+  uint16_t* s1_hi[kMaxKB][2];
+  uint16_t* s1_lo[kMaxKB][2];
+  const TileItem* items;             // this problem's tile items in its class list
+  int32_t n_items;
+  int32_t slot_first;                // partial slot of items[0]
   int64_t n, np, ld;
   double nocc;
   int32_t k;
   int32_t h0_index, h1_first;        // positions in the input / output pointer tables
   int32_t u0_first, u0_count;        // S0 block-table range
+  int32_t tr_first, tr_count;        // range of this problem's diagonal blocks of Tr X
   int32_t u1_first[kMaxKB], u1_count[kMaxKB];
 };
 
@@ -39,6 +42,7 @@ struct Chunk {
   int32_t p, j;                      // problem, matrix (-1: S0, j: S1_j)
   int64_t q0, q1;                    // range of 4-element vectors of the padded storage
 };
+
 
 struct ProblemSummary {
   int32_t layers, d0_layer, converged, error;
@@ -141,7 +145,7 @@ __global__ void __launch_bounds__(kBlk) k_b_s1setup(const BatchProblem* P, const
 }
 
 // S0 = (eps_N I - H0)/(eps_N - eps_1) (j = -1) or S1_0 = -H1_j/(eps_N - eps_1),
-// FP32 master plus panel-major hi/lo.
+// FP32 master plus panel-major hi/lo (buffers 0).
 template <typename T16>
 __global__ void __launch_bounds__(kBlk) k_b_init(const BatchProblem* P, const Chunk* C,
                                                 const double* const* h0tab,
@@ -152,8 +156,8 @@ __global__ void __launch_bounds__(kBlk) k_b_init(const BatchProblem* P, const Ch
   const double en = st->epsN, w = st->epsN - st->eps1;
   const double* H = c.j < 0 ? h0tab[b.h0_index] : h1tab[b.h1_first + c.j];
   float* m = c.j < 0 ? b.s_master : b.s1buf[c.j][0];
-  uint16_t* hi = c.j < 0 ? b.s_hi : b.s1_hi[c.j];
-  uint16_t* lo = c.j < 0 ? b.s_lo : b.s1_lo[c.j];
+  uint16_t* hi = c.j < 0 ? b.s_hi[0] : b.s1_hi[c.j][0];
+  uint16_t* lo = c.j < 0 ? b.s_lo[0] : b.s1_lo[c.j][0];
   const int e = c.j < 0 ? 0 : st->s1_exp_split[c.j];
   for (int64_t q = c.q0 * 4 + threadIdx.x; q < c.q1 * 4; q += kBlk) {
     const int64_t r = q / b.ld, col = q - r * b.ld;
@@ -169,42 +173,19 @@ __global__ void __launch_bounds__(kBlk) k_b_init(const BatchProblem* P, const Ch
   }
 }
 
-// ------------------------------------------------------------------ layer kernels
-__global__ void __launch_bounds__(kBlk) k_b_decide0(const BatchProblem* P) {
+// ------------------------------------------------------------------ layer decisions
+// Before the products of a layer: N_X from this problem's diagonal-block
+// partials of Tr X (launch_trace_diag).
+__global__ void __launch_bounds__(kBlk) k_b_predecide(const BatchProblem* P, const double* part) {
   const BatchProblem& b = P[blockIdx.x];
-  decide0_body<float>(b.st, b.x, b.ld);
+  predecide_body(b.st, part + b.tr_first, b.tr_count);
 }
 
-template <typename T16>
-__global__ void __launch_bounds__(kBlk) k_b_update(const BatchProblem* P, const Chunk* C,
-                                                  double* pfro, double* pmax, int t, int layer) {
-  const Chunk c = C[blockIdx.x];
-  const BatchProblem& b = P[c.p];
-  const int64_t q0 = c.q0 + threadIdx.x;
-  if (c.j < 0) {
-    update_body<float, T16, true>(b.st, -1, b.x, b.s_master, b.s_master, b.s_hi, b.s_lo, q0, c.q1,
-                                  kBlk, b.ld, b.np, t, pfro + blockIdx.x, nullptr);
-  } else {
-    const int cur = layer & 1;
-    float* s1 = b.s1buf[c.j][cur];
-    update_body<float, T16, true>(b.st, c.j, s1, b.s1buf[c.j][cur ^ 1], s1, b.s1_hi[c.j],
-                                  b.s1_lo[c.j], q0, c.q1, kBlk, b.ld, b.np, t, pfro + blockIdx.x,
-                                  pmax + blockIdx.x);
-  }
-}
-
-__global__ void __launch_bounds__(kBlk) k_b_decide1(const BatchProblem* P, const double* p0,
-                                                   const double* p1f, const double* p1m, int t) {
+// After the products: this problem's item partials.
+__global__ void __launch_bounds__(kBlk) k_b_postdecide(const BatchProblem* P, const double* part_f,
+                                                      const double* part_m, int t) {
   const BatchProblem& b = P[blockIdx.x];
-  Partials pr;
-  pr.fro0 = p0 + b.u0_first;
-  pr.n0 = b.u0_count;
-  for (int j = 0; j < kMaxK; ++j) {
-    pr.fro1[j] = j < b.k ? p1f + b.u1_first[j] : p1f;
-    pr.max1[j] = j < b.k ? p1m + b.u1_first[j] : p1m;
-    pr.n1[j] = j < b.k ? b.u1_count[j] : 0;
-  }
-  decide1_body(b.st, pr, 1, t);
+  postdecide_body(b.st, b.items, b.n_items, part_f + b.slot_first, part_m + b.slot_first, t);
 }
 
 // ------------------------------------------------------------------ outputs
@@ -304,10 +285,13 @@ struct dmpt_batch {
   std::vector<Chunk> c0, c1;
   Chunk* dc0 = nullptr;
   Chunk* dc1 = nullptr;
-  double* part0 = nullptr;
-  double* part1f = nullptr;
-  double* part1m = nullptr;
-  ProblemDesc* desc[2] = {nullptr, nullptr};   // by layer parity
+  std::vector<TraceBlock> tb;                  // diagonal blocks of Tr X
+  TraceBlock* dtb = nullptr;
+  double* part_tr = nullptr;                   // per diagonal block: trace partial
+  double* part1m = nullptr;                    // per S1 chunk: max |H1|
+  double* part_f = nullptr;                    // per tile item: fused-layer partials
+  double* part_m = nullptr;
+  ProblemDesc* desc = nullptr;                 // per problem: buffers of the fused layer
   int threshold = 0;                           // problems with Np <= threshold use 128-row tiles
   TileItem* items[2] = {nullptr, nullptr};     // [0]: 256-row tiles, [1]: 128-row tiles
   int n_items[2] = {0, 0};
@@ -351,73 +335,81 @@ void batch_free(dmpt_batch* b) {
   delete b;
 }
 
-// Item lists of the two tile classes for a given threshold.
-hipError_t build_class_items(dmpt_batch* b, int threshold, bool upload) {
-  std::vector<TileItem> big, small;
+// Item lists of the two tile classes for a given threshold, each problem's
+// item range, and the per-problem buffer descriptors (the k extent follows
+// the class).
+hipError_t build_class_items(dmpt_batch* b, int threshold) {
+  std::vector<TileItem> cls[2];
+  std::vector<int> first(b->count), count(b->count), which(b->count);
   for (int p = 0; p < b->count; ++p) {
     const BatchProblem& bp = b->hp[p];
-    const bool sm = bp.np <= threshold;
-    const int tile = sm ? 128 : 256;
+    const int c = bp.np <= threshold ? 1 : 0;
+    const int tile = c ? 128 : 256;
     const int T = (int)((bp.n + tile - 1) / tile);
     std::vector<TileItem> v = triangle_items(T, bp.k, p);
-    (sm ? small : big).insert((sm ? small : big).end(), v.begin(), v.end());
+    which[p] = c;
+    first[p] = (int)cls[c].size();
+    count[p] = (int)v.size();
+    cls[c].insert(cls[c].end(), v.begin(), v.end());
   }
   b->threshold = threshold;
-  b->n_items[0] = (int)big.size();
-  b->n_items[1] = (int)small.size();
-  if (!upload) return hipSuccess;
+  b->n_items[0] = (int)cls[0].size();
+  b->n_items[1] = (int)cls[1].size();
   hipError_t e = hipSuccess;
-  if (!big.empty())
-    e = hipMemcpy(b->items[0], big.data(), big.size() * sizeof(TileItem), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !small.empty())
-    e = hipMemcpy(b->items[1], small.data(), small.size() * sizeof(TileItem),
-                  hipMemcpyHostToDevice);
+  for (int c = 0; c < 2 && e == hipSuccess; ++c)
+    if (!cls[c].empty())
+      e = hipMemcpy(b->items[c], cls[c].data(), cls[c].size() * sizeof(TileItem),
+                    hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
-  // the k extent of each problem follows its class
-  std::vector<ProblemDesc> d[2];
-  for (int par = 0; par < 2; ++par) {
-    d[par].resize(b->count);
-    for (int p = 0; p < b->count; ++p) {
-      const BatchProblem& bp = b->hp[p];
-      ProblemDesc& q = d[par][p];
-      memset(&q, 0, sizeof(q));
-      q.s_hi = bp.s_hi;
-      q.s_lo = bp.s_lo;
+  std::vector<ProblemDesc> d(b->count);
+  for (int p = 0; p < b->count; ++p) {
+    BatchProblem& bp = b->hp[p];
+    bp.items = b->items[which[p]] + first[p];
+    bp.n_items = count[p];
+    bp.slot_first = (which[p] ? b->n_items[0] : 0) + first[p];
+    ProblemDesc& q = d[p];
+    memset(&q, 0, sizeof(q));
+    for (int par = 0; par < 2; ++par) {
+      q.s_hi[par] = bp.s_hi[par];
+      q.s_lo[par] = bp.s_lo[par];
       for (int j = 0; j < bp.k; ++j) {
-        q.s1_hi[j] = bp.s1_hi[j];
-        q.s1_lo[j] = bp.s1_lo[j];
-        q.x1[j] = bp.s1buf[j][par];
+        q.s1_hi[j][par] = bp.s1_hi[j][par];
+        q.s1_lo[j][par] = bp.s1_lo[j][par];
+        q.s1m[j][par] = bp.s1buf[j][par];
       }
-      q.x = bp.x;
-      q.state = bp.st;
-      q.ld = bp.ld;
-      const int tile = bp.np <= threshold ? 128 : 256;
-      q.kdim = (bp.n + tile - 1) / tile * tile;
-      q.pdim = bp.np;
     }
-    e = hipMemcpy(b->desc[par], d[par].data(), b->count * sizeof(ProblemDesc),
-                  hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
+    q.s_master = bp.s_master;
+    q.state = bp.st;
+    q.ld = bp.ld;
+    const int tile = which[p] ? 128 : 256;
+    q.kdim = (bp.n + tile - 1) / tile * tile;
+    q.pdim = bp.np;
   }
-  return hipSuccess;
+  e = hipMemcpy(b->desc, d.data(), b->count * sizeof(ProblemDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->dp, b->hp.data(), sizeof(BatchProblem) * b->count, hipMemcpyHostToDevice);
+  return e;
 }
 
-hipError_t launch_products_all(dmpt_batch* b, int parity, bool with_state, hipStream_t s) {
-  (void)with_state;
+hipError_t launch_products_all(dmpt_batch* b, hipStream_t s) {
   ProductArgs a;
   memset(&a, 0, sizeof(a));
-  a.probs = b->desc[parity];
+  a.probs = b->desc;
+  a.part_f = b->part_f;
+  a.part_m = b->part_m;
   a.lo_shift = b->t;
   hipError_t e = hipSuccess;
   if (b->n_items[0] > 0) {
     a.items = b->items[0];
     a.n_items = b->n_items[0];
-    e = launch_products_batch(b->prec, 256, a, s);
+    a.slot_base = 0;
+    e = launch_products_fused(b->prec, 256, a, s);
   }
   if (e == hipSuccess && b->n_items[1] > 0) {
     a.items = b->items[1];
     a.n_items = b->n_items[1];
-    e = launch_products_batch(b->prec, 128, a, s);
+    a.slot_base = b->n_items[0];
+    e = launch_products_fused(b->prec, 128, a, s);
   }
   return e;
 }
@@ -426,36 +418,29 @@ template <typename T16>
 hipError_t enqueue_response(dmpt_batch* b, hipStream_t s) {
   const int P = b->count;
   hipLaunchKernelGGL(k_b_setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->h0tab, b->max_layers);
-  if (!b->c1.empty()) {
-    hipLaunchKernelGGL(k_b_maxabs1, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1,
-                       b->h1tab, b->part1m);
-    hipLaunchKernelGGL(k_b_s1setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->part1m);
-  }
+  hipLaunchKernelGGL(k_b_maxabs1, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1, b->h1tab,
+                     b->part1m);
+  hipLaunchKernelGGL(k_b_s1setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->part1m);
   hipLaunchKernelGGL(k_b_init<T16>, dim3(b->c0.size()), dim3(kBlk), 0, s, b->dp, b->dc0, b->h0tab,
                      b->h1tab, b->t);
-  if (!b->c1.empty())
-    hipLaunchKernelGGL(k_b_init<T16>, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1,
-                       b->h0tab, b->h1tab, b->t);
+  hipLaunchKernelGGL(k_b_init<T16>, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1, b->h0tab,
+                     b->h1tab, b->t);
   hipError_t e = hipGetLastError();
   for (int n = 1; n <= b->max_layers && e == hipSuccess; ++n) {
-    e = launch_products_all(b, n & 1, true, s);
+    e = launch_trace_diag(b->prec, b->desc, b->dtb, (int)b->tb.size(), b->part_tr, s);
     if (e != hipSuccess) break;
-    hipLaunchKernelGGL(k_b_decide0, dim3(P), dim3(kBlk), 0, s, b->dp);
-    hipLaunchKernelGGL(k_b_update<T16>, dim3(b->c0.size()), dim3(kBlk), 0, s, b->dp, b->dc0,
-                       b->part0, (double*)nullptr, b->t, n);
-    if (!b->c1.empty())
-      hipLaunchKernelGGL(k_b_update<T16>, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1,
-                         b->part1f, b->part1m, b->t, n);
-    hipLaunchKernelGGL(k_b_decide1, dim3(P), dim3(kBlk), 0, s, b->dp, b->part0, b->part1f,
-                       b->part1m, b->t);
+    hipLaunchKernelGGL(k_b_predecide, dim3(P), dim3(kBlk), 0, s, b->dp, b->part_tr);
+    e = launch_products_all(b, s);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_b_postdecide, dim3(P), dim3(kBlk), 0, s, b->dp, b->part_f, b->part_m,
+                       b->t);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_b_out, dim3(b->c0.size()), dim3(kBlk), 0, s, b->dp, b->dc0, b->p0tab,
                      b->p1tab);
-  if (!b->c1.empty())
-    hipLaunchKernelGGL(k_b_out, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1, b->p0tab,
-                       b->p1tab);
+  hipLaunchKernelGGL(k_b_out, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1, b->p0tab,
+                     b->p1tab);
   hipLaunchKernelGGL(k_b_summary, dim3(P), dim3(kWave), 0, s, b->dp, b->dsum);
   return hipGetLastError();
 }
@@ -465,10 +450,11 @@ hipError_t enqueue(dmpt_batch* b, hipStream_t s) {
                                     : enqueue_response<__bf16>(b, s);
 }
 
-// Tile-class autotuner: time one product sweep over the whole batch for each
-// candidate threshold (problems with padded size <= threshold use 128-row
-// tiles) and keep the fastest.  Operands are the zero-initialised workspace;
-// MFMA timing does not depend on the values.
+// Tile-class autotuner: time one fused product sweep over the whole batch for
+// each candidate threshold (problems with padded size <= threshold use
+// 128-row tiles) and keep the fastest.  It runs on the zero-initialised
+// workspace with a cleared state (every tile active, all values zero), before
+// any response; MFMA timing does not depend on the values.
 hipError_t autotune(dmpt_batch* b) {
   int maxnp = 0;
   for (auto& p : b->hp) maxnp = std::max<int>(maxnp, (int)p.np);
@@ -483,12 +469,12 @@ hipError_t autotune(dmpt_batch* b) {
   b->tune_ms.clear();
   b->tune_cand = cand;
   for (int th : cand) {
-    e = build_class_items(b, th, true);
+    e = build_class_items(b, th);
     if (e != hipSuccess) break;
-    e = launch_products_all(b, 0, false, b->stream);      // warm-up
+    e = launch_products_all(b, b->stream);      // warm-up
     if (e != hipSuccess) break;
     e = hipEventRecord(e0, b->stream);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_products_all(b, r & 1, false, b->stream);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_products_all(b, b->stream);
     if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e != hipSuccess) break;
@@ -503,7 +489,7 @@ hipError_t autotune(dmpt_batch* b) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (e != hipSuccess) return e;
-  return build_class_items(b, best_th, true);
+  return build_class_items(b, best_th);
 }
 
 }  // namespace
@@ -554,12 +540,15 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
     q.h1_first = h1;
     h1 += k[p];
     const size_t m = (size_t)q.np * q.ld;
-    f32 += m * (2 + 2 * q.k);
-    u16 += (size_t)q.np * q.np * 2 * (1 + q.k);
+    f32 += m * (1 + 2 * q.k);                          // S, S1_j x 2
+    u16 += (size_t)q.np * q.np * 4 * (1 + q.k);        // hi, lo x 2 buffers of S and S1_j
     const int64_t vec = m / 4;
     const int nch = (int)((vec + kChunkVec - 1) / kChunkVec);
     q.u0_first = (int)b->c0.size();
     q.u0_count = nch;
+    q.tr_first = (int)b->tb.size();
+    q.tr_count = (int)((q.n + 31) / 32);
+    for (int r = 0; r < q.tr_count; ++r) b->tb.push_back(TraceBlock{p, r});
     for (int c = 0; c < nch; ++c)
       b->c0.push_back(Chunk{p, -1, (int64_t)c * kChunkVec, std::min<int64_t>(vec, (int64_t)(c + 1) * kChunkVec)});
     for (int j = 0; j < q.k; ++j) {
@@ -582,12 +571,11 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
   get((void**)&sbase, sizeof(LayerState) * count);
   get((void**)&b->dp, sizeof(BatchProblem) * count);
   get((void**)&b->dc0, sizeof(Chunk) * b->c0.size());
-  get((void**)&b->dc1, sizeof(Chunk) * std::max<size_t>(1, b->c1.size()));
-  get((void**)&b->part0, sizeof(double) * b->c0.size());
-  get((void**)&b->part1f, sizeof(double) * std::max<size_t>(1, b->c1.size()));
-  get((void**)&b->part1m, sizeof(double) * std::max<size_t>(1, b->c1.size()));
-  get((void**)&b->desc[0], sizeof(ProblemDesc) * count);
-  get((void**)&b->desc[1], sizeof(ProblemDesc) * count);
+  get((void**)&b->dc1, sizeof(Chunk) * b->c1.size());
+  get((void**)&b->dtb, sizeof(TraceBlock) * b->tb.size());
+  get((void**)&b->part_tr, sizeof(double) * b->tb.size());
+  get((void**)&b->part1m, sizeof(double) * b->c1.size());
+  get((void**)&b->desc, sizeof(ProblemDesc) * count);
   size_t n_big = 0, n_small = 0;
   for (auto& q : b->hp) {
     const int Tb = (int)((q.n + 255) / 256), Ts = (int)((q.n + 127) / 128);
@@ -596,6 +584,8 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
   }
   get((void**)&b->items[0], sizeof(TileItem) * n_big);
   get((void**)&b->items[1], sizeof(TileItem) * n_small);
+  get((void**)&b->part_f, sizeof(double) * (n_big + n_small));
+  get((void**)&b->part_m, sizeof(double) * (n_big + n_small));
   get((void**)&b->h0tab, sizeof(void*) * count);
   get((void**)&b->p0tab, sizeof(void*) * count);
   get((void**)&b->h1tab, sizeof(void*) * h1);
@@ -613,27 +603,28 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
     const size_t m = (size_t)q.np * q.ld, pm = (size_t)q.np * q.np;
     q.st = sbase + p;
     q.s_master = fbase + fo; fo += m;
-    q.x = fbase + fo; fo += m;
     for (int j = 0; j < q.k; ++j) {
       q.s1buf[j][0] = fbase + fo; fo += m;
       q.s1buf[j][1] = fbase + fo; fo += m;
     }
-    q.s_hi = hbase + ho; ho += pm;
-    q.s_lo = hbase + ho; ho += pm;
-    for (int j = 0; j < q.k; ++j) {
-      q.s1_hi[j] = hbase + ho; ho += pm;
-      q.s1_lo[j] = hbase + ho; ho += pm;
+    for (int par = 0; par < 2; ++par) {
+      q.s_hi[par] = hbase + ho; ho += pm;
+      q.s_lo[par] = hbase + ho; ho += pm;
+      for (int j = 0; j < q.k; ++j) {
+        q.s1_hi[j][par] = hbase + ho; ho += pm;
+        q.s1_lo[j][par] = hbase + ho; ho += pm;
+      }
     }
   }
   // the products never write outside each problem's k extent: start from zero
   if (hipMemset(fbase, 0, f32 * 4) != hipSuccess || hipMemset(hbase, 0, u16 * 2) != hipSuccess ||
       hipMemset(sbase, 0, sizeof(LayerState) * count) != hipSuccess ||
-      hipMemcpy(b->dp, b->hp.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice) !=
-          hipSuccess ||
       hipMemcpy(b->dc0, b->c0.data(), sizeof(Chunk) * b->c0.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
-      (!b->c1.empty() && hipMemcpy(b->dc1, b->c1.data(), sizeof(Chunk) * b->c1.size(),
-                                   hipMemcpyHostToDevice) != hipSuccess))
+      hipMemcpy(b->dc1, b->c1.data(), sizeof(Chunk) * b->c1.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->dtb, b->tb.data(), sizeof(TraceBlock) * b->tb.size(), hipMemcpyHostToDevice) !=
+          hipSuccess)
     return bail(DMPT_EHIP, "workspace set-up failed");
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)

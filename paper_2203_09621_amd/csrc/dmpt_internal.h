@@ -63,6 +63,8 @@ struct LayerState {
   int32_t upd_s0;            // S0 is updated at layer n
   int32_t d0_now;            // the D0 test fired at layer n
   int32_t sigma_cur;         // sigma_n
+  int32_t s_par;             // fused split forms: buffer of the current 16-bit split of S
+  int32_t pad1;
   double n_s;                // tracked occupation N_S
   double n_s0;               // Tr S0 of the normalisation layer
   double fro0;               // ||S - S^2||_F at the D0 layer
@@ -88,16 +90,26 @@ struct TileItem {
 
 constexpr int kMaxKB = 3;    // most responses per problem of a batch
 
-// Operands of one problem in a batched product launch.
+// One 32-row diagonal block of X = S^2 whose diagonal enters Tr X.
+struct TraceBlock {
+  int32_t prob;
+  int32_t blk;               // rows 32 blk .. 32 blk + 31
+};
+
+// Buffers of one problem for the fused layer (split forms): the products
+// read the current 16-bit splits and their epilogue writes the updated FP32
+// masters and the next splits.  The split of S alternates between its two
+// buffers with every update of S (LayerState::s_par); the split and master of
+// S1_j alternate with the layer parity (S1_n lives in buffers n & 1).
 struct ProblemDesc {
-  const void* s_hi;
-  const void* s_lo;
-  const void* s1_hi[kMaxKB];
-  const void* s1_lo[kMaxKB];
-  void* x;
-  void* x1[kMaxKB];
-  const LayerState* state;
-  int64_t ld;                // row stride of X and X1
+  const void* s_hi[2];
+  const void* s_lo[2];
+  const void* s1_hi[kMaxK][2];
+  const void* s1_lo[kMaxK][2];
+  float* s_master;           // S, updated in place (each tile owns its block and its mirror)
+  float* s1m[kMaxK][2];      // S1_j masters
+  LayerState* state;
+  int64_t ld;                // row stride of the masters
   int64_t kdim;              // k extent of the products (multiple of the tile)
   int64_t pdim;              // panel-layout size of the 16-bit operands (multiple of 256)
 };
@@ -112,7 +124,11 @@ struct ProductArgs {
   void* x;                   // X (FP32 or FP64)
   void* x1[kMaxK];           // X1_j
   const void* a_op[kMaxK];    // direct forms: A operand of output 1 + j (NULL: S)
-  const ProblemDesc* probs;  // split forms, batched: per-item operands (NULL: the fields here)
+  const ProblemDesc* probs;  // fused split layer: per-problem buffers (NULL: the fields here)
+  double* part_f;            // fused: per-item FP64 sums (squares), slot slot_base + item
+  double* part_m;            // fused: per-item max |S1_new|
+  int32_t slot_base;
+  int32_t pad0;
   const TileItem* items;
   const LayerState* state;   // NULL: compute every item, scales taken from s1_exp
   int32_t s1_exp[kMaxK];     // used when state == NULL
@@ -126,9 +142,18 @@ struct ProductArgs {
 // layer products (kernels_gemm.hip)
 int product_tile(dmpt_precision prec);   // output tile edge used by the product kernels
 hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s);
-// batched split products with 256- or 128-row tiles (a.probs set)
-hipError_t launch_products_batch(dmpt_precision prec, int tile, const ProductArgs& a,
+// Fused split layer with 256- or 128-row tiles (a.probs set): the products of
+// layer n and, in their epilogue, the layer update, the next split and the
+// per-item partial sums; sigma and the update flags come from each problem's
+// state, decided before the launch.
+hipError_t launch_products_fused(dmpt_precision prec, int tile, const ProductArgs& a,
                                  hipStream_t s);
+// N_X = Tr X_n of the coming fused products, before them: the diagonal 32 x 32
+// fragments of X_n = S_{n-1}^2, one wave each, with the product kernel's MFMA
+// sequence, so every X_ii equals the product's bitwise; part[b] = FP64 sum of
+// the diagonal of block b (problems with D0 open).
+hipError_t launch_trace_diag(dmpt_precision prec, const ProblemDesc* probs,
+                             const TraceBlock* blocks, int n_blocks, double* part, hipStream_t s);
 
 // layer kernels (kernels_layer.hip)
 hipError_t launch_gershgorin(const double* H, int64_t n, double* partial /* 3*512 */,
@@ -153,6 +178,12 @@ hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, c
                          int64_t ld, int t, double* pfro, double* pmax, hipStream_t s);
 hipError_t launch_decide1(LayerState* st, const double* pfro0, const double* pfro1,
                           const double* pmax1, int split, int lo_shift, hipStream_t s);
+// Fused split layer: the decisions before the products (N_X from np trace
+// partials) and after them (item partials of `items`, slot = index).
+hipError_t launch_predecide(LayerState* st, const double* part, int np, hipStream_t s);
+hipError_t launch_postdecide(LayerState* st, const TileItem* items, int n_items,
+                             const double* part_f, const double* part_m, int lo_shift,
+                             hipStream_t s);
 hipError_t launch_copy_out(dmpt_precision prec, const LayerState* st, int which, const void* b0,
                            const void* b1, int64_t ld, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_trace(const double* P, int64_t n, double* out, hipStream_t s);

@@ -17,7 +17,7 @@
 // as in the paper.  The 2^t factor is applied to hi_A in registers (exact).
 #include <stdlib.h>
 
-#include "dmpt_internal.h"
+#include "layer_common.h"
 
 namespace dmpt {
 
@@ -56,12 +56,20 @@ template <> struct Split16<__bf16> {
 };
 
 // Resolve the skip flags and the operand scale of one tile item.
-// Returns false when the item has nothing to do.
+// Returns false when the item has nothing to do.  Plain launches run after
+// nothing was decided for the layer: X is skipped once D0 converged.  Fused
+// launches run after the decision of layer n: X is still formed at the D0
+// layer itself, for ||S - X||_F.
+template <bool FUSED>
 __device__ __forceinline__ bool item_active(const ProductArgs& a, const TileItem& it, int* sexp) {
-  const LayerState* st = a.probs ? a.probs[it.prob].state : a.state;
+  const LayerState* st = FUSED ? a.probs[it.prob].state : a.state;
   if (st) {
     if (st->done) return false;
-    if (it.out == 0 ? st->d0 : st->d1[it.out - 1]) return false;
+    if (it.out == 0) {
+      if (FUSED ? (st->d0 && !st->d0_now) : st->d0) return false;
+    } else if (st->d1[it.out - 1]) {
+      return false;
+    }
     *sexp = it.out == 0 ? 0 : st->s1_exp_split[it.out - 1];
   } else {
     *sexp = it.out == 0 ? 0 : a.s1_exp[it.out - 1];
@@ -77,7 +85,14 @@ struct VmWait {
   static constexpr int imm = (N & 15) | (((N >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
 };
 
-template <typename T16, int BM, int BK, int WGM, int WGN, int SWZ, int STAGES>
+// Plain launches store X and X1_j.  Fused launches (FUSED) apply the layer
+// update in the epilogue instead: with sigma of the problem's state,
+//   S_n  = X    (sigma = +1)   or  2 S_{n-1}  - X     (sigma = -1)
+//   S1_n = X1_j (sigma = +1)   or  2 S1_{n-1} - X1_j  (sigma = -1)
+// (Eqs. LinTransf, S_n detailed, dB), written to the FP32 masters and split
+// into the next 16-bit buffers with the state's scale, together with FP64
+// partial sums for the decisions; X and X1 never reach memory.
+template <typename T16, int BM, int BK, int WGM, int WGN, int SWZ, int STAGES, bool FUSED>
 __global__ void __launch_bounds__(WGM * WGN * kWave)
 k_products_split(const ProductArgs a) {
   using S = Split16<T16>;
@@ -113,26 +128,29 @@ k_products_split(const ProductArgs a) {
   for (int item_id = slot; item_id < a.n_items; item_id += gridDim.x) {
   const TileItem it = a.items[item_id];
   int sexp = 0;
-  if (!item_active(a, it, &sexp)) continue;
+  if (!item_active<FUSED>(a, it, &sexp)) continue;
 
   const int j = it.out - 1;
   const int nprod = it.out == 0 ? 1 : 2;
-  // operands of this item: the batch descriptor or the single-problem fields
-  const ProblemDesc* pd = a.probs ? a.probs + it.prob : nullptr;
-  const int64_t ld = pd ? pd->ld : a.ld;
-  const int64_t kdim = pd ? pd->kdim : a.kdim;
-  const int64_t pdim = pd ? pd->pdim : a.kdim;
+  // operands of this item: the problem's descriptor (fused) or the launch fields
+  const ProblemDesc* pd = FUSED ? a.probs + it.prob : nullptr;
+  const LayerState* fst = FUSED ? pd->state : nullptr;
+  const int64_t ld = FUSED ? pd->ld : a.ld;
+  const int64_t kdim = FUSED ? pd->kdim : a.kdim;
+  const int64_t pdim = FUSED ? pd->pdim : a.kdim;
   // operand panels per product: [hi_A, lo_A, hi_B, lo_B]
   const uint16_t* P[2][4];
   {
-    const uint16_t* sh = (const uint16_t*)(pd ? pd->s_hi : a.s_hi);
-    const uint16_t* sl = (const uint16_t*)(pd ? pd->s_lo : a.s_lo);
+    const int sp = FUSED ? fst->s_par : 0;
+    const int lp = FUSED ? ((fst->n - 1) & 1) : 0;   // S1_{n-1} split
+    const uint16_t* sh = (const uint16_t*)(FUSED ? pd->s_hi[sp] : a.s_hi);
+    const uint16_t* sl = (const uint16_t*)(FUSED ? pd->s_lo[sp] : a.s_lo);
     if (it.out == 0) {
       P[0][0] = sh; P[0][1] = sl; P[0][2] = sh; P[0][3] = sl;
       P[1][0] = sh; P[1][1] = sl; P[1][2] = sh; P[1][3] = sl;
     } else {
-      const uint16_t* th = (const uint16_t*)(pd ? pd->s1_hi[j] : a.s1_hi[j]);
-      const uint16_t* tl = (const uint16_t*)(pd ? pd->s1_lo[j] : a.s1_lo[j]);
+      const uint16_t* th = (const uint16_t*)(FUSED ? pd->s1_hi[j][lp] : a.s1_hi[j]);
+      const uint16_t* tl = (const uint16_t*)(FUSED ? pd->s1_lo[j][lp] : a.s1_lo[j]);
       P[0][0] = sh; P[0][1] = sl; P[0][2] = th; P[0][3] = tl;
       P[1][0] = th; P[1][1] = tl; P[1][2] = sh; P[1][3] = sl;
     }
@@ -231,10 +249,11 @@ k_products_split(const ProductArgs a) {
     __syncthreads();
   }
 
-  // epilogue: unscale, store the tile and its mirror image
   const float scale = ldexpf(1.0f, -(S::kShift + sexp));
-  float* C = (float*)(pd ? (it.out == 0 ? pd->x : pd->x1[j]) : (it.out == 0 ? a.x : a.x1[j]));
   const bool diag = it.ti == it.tj;
+  if constexpr (!FUSED) {
+  // epilogue: unscale, store the tile and its mirror image
+  float* C = (float*)(it.out == 0 ? a.x : a.x1[j]);
 #pragma unroll
   for (int m = 0; m < FM; ++m)
 #pragma unroll
@@ -260,6 +279,158 @@ k_products_split(const ProductArgs a) {
         }
       }
     }
+  } else {
+  // Fused epilogue: the layer update of this tile and of its mirror image.
+  // The tile goes through LDS (free after the main loop) in FM rounds: in
+  // round m every wave parks its 32-row fragment strip m, row-major, and the
+  // workgroup then updates those SR rows (direct block, row-major) and their
+  // mirror columns (transposed reads), with coalesced global accesses.
+  // Element (lr, lc) of the upper triangle stands for itself and its mirror,
+  // so the norms weigh it 2 (off the diagonal) or 1 (on it).
+  constexpr int SR = 32 * WGM;               // tile rows staged per round
+  constexpr int PT = BN + 4;                 // LDS row pitch (floats)
+  constexpr int ITER = SR * BN / (4 * NT);   // float4 groups per thread and round
+  constexpr int G = ITER < 4 ? ITER : 4;
+  static_assert(SR * BN % (4 * NT) == 0 && ITER % G == 0, "whole float4 groups per thread");
+  static_assert(SR * PT * 4 <= STAGES * STAGE * 16, "staging fits in the operand LDS");
+  float* T = (float*)lds;
+  const int sig = fst->sigma_cur;
+  const bool isx = it.out == 0;
+  const bool upd = isx ? fst->upd_s0 != 0 : true;
+  // ||S - X||_F^2 at the D0 layer, ||S1_j - X1_j||_F^2 once D0 converged
+  const bool diff = isx ? !upd : fst->d0 != 0;
+  const bool need_old = diff || sig < 0;
+  const int cur = fst->n & 1;
+  const float* Mr = isx ? pd->s_master : pd->s1m[j][cur ^ 1];
+  float* Mw = isx ? pd->s_master : pd->s1m[j][cur];
+  uint16_t* Hw = (uint16_t*)(isx ? pd->s_hi[fst->s_par ^ 1] : pd->s1_hi[j][cur]);
+  uint16_t* Lw = (uint16_t*)(isx ? pd->s_lo[fst->s_par ^ 1] : pd->s1_lo[j][cur]);
+  const int esplit = isx ? 0 : fst->s1_exp_next[j];
+  typedef uint16_t U4 __attribute__((ext_vector_type(4)));
+  double pf = 0.0;
+  float pm = 0.0f;
+#pragma unroll
+  for (int m = 0; m < FM; ++m) {
+    // park: wave (wm, wn) writes rows wm*32 + [0, 32) of T, columns of its fragments
+#pragma unroll
+    for (int n = 0; n < FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        T[row * PT + wn * WTN + n * 32 + (lane & 31)] = acc[m][n][r] * scale;
+      }
+    __syncthreads();
+    // direct block: T row tr is tile row (tr / 32) * WTM + m * 32 + tr % 32.
+    // Groups of G float4 per thread: the G old-value loads go out together.
+#pragma unroll 1
+    for (int g0 = 0; g0 < ITER; g0 += G) {
+      f32x4 sov[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int e = (tid + (g0 + i) * NT) * 4;
+        const int tr = e / BN, lc = e % BN;
+        const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
+        sov[i] = need_old ? *(const f32x4*)(Mr + (row_a0 + lr) * ld + row_b0 + lc)
+                          : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int e = (tid + (g0 + i) * NT) * 4;
+        const int tr = e / BN, lc = e % BN;
+        const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
+        const f32x4 x = *(const f32x4*)(T + tr * PT + lc);
+        const int64_t grow = row_a0 + lr, gcol = row_b0 + lc;
+        const f32x4 so = sov[i];
+        f32x4 sn;
+        uint16_t h[4], l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          sn[q] = sig > 0 ? x[q] : 2.0f * so[q] - x[q];
+          const int c = lc + q;
+          const double w = diag ? (lr < c ? 2.0 : (lr == c ? 1.0 : 0.0)) : 2.0;
+          const double d = (double)so[q] - (double)x[q];
+          if (diff) pf += w * d * d;
+          if (w > 0.0) pm = fmaxf(pm, fabsf(sn[q]));
+          split_one<T16>(sn[q], esplit, S::kShift, h + q, l + q);
+        }
+        if (!upd) continue;
+        *(f32x4*)(T + tr * PT + lc) = sn;      // for the mirror pass
+        const int64_t pi = panel_index(grow, gcol, pdim);   // four columns, one panel row
+        if (!diag || lr < lc) {
+          *(f32x4*)(Mw + grow * ld + gcol) = sn;
+          *(U4*)(Hw + pi) = U4{h[0], h[1], h[2], h[3]};
+          *(U4*)(Lw + pi) = U4{l[0], l[1], l[2], l[3]};
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (lr <= lc + q) {
+              Mw[grow * ld + gcol + q] = sn[q];
+              Hw[pi + q] = h[q];
+              Lw[pi + q] = l[q];
+            }
+        }
+      }
+    }
+    __syncthreads();
+    // mirror block: row lc of the mirror gets T rows 4 qd .. 4 qd + 3 of column lc
+    if (upd) {
+      for (int e = tid; e < BN * (SR / 4); e += NT) {
+        const int qd = e % (SR / 4), lc = e / (SR / 4);
+        const int tr = 4 * qd;
+        const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
+        if (diag && lr >= lc) continue;        // lr + q < lc for some q needs lr < lc
+        f32x4 v;
+        uint16_t h[4], l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          v[q] = T[(tr + q) * PT + lc];
+          split_one<T16>(v[q], esplit, S::kShift, h + q, l + q);
+        }
+        const int64_t grow = row_b0 + lc, gcol = row_a0 + lr;
+        const int64_t pi = panel_index(grow, gcol, pdim);
+        if (!diag || lr + 3 < lc) {
+          *(f32x4*)(Mw + grow * ld + gcol) = v;
+          *(U4*)(Hw + pi) = U4{h[0], h[1], h[2], h[3]};
+          *(U4*)(Lw + pi) = U4{l[0], l[1], l[2], l[3]};
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (lr + q < lc) {
+              Mw[grow * ld + gcol + q] = v[q];
+              Hw[pi + q] = h[q];
+              Lw[pi + q] = l[q];
+            }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // workgroup partials in a fixed order: butterfly within each wave, then the
+  // waves in index order
+  __shared__ double red_f[WGM * WGN];
+  __shared__ float red_m[WGM * WGN];
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    pf += __shfl_xor(pf, o);
+    pm = fmaxf(pm, __shfl_xor(pm, o));
+  }
+  if (lane == 0) {
+    red_f[wave] = pf;
+    red_m[wave] = pm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double f = 0.0;
+    float mx = 0.0f;
+#pragma unroll
+    for (int w = 0; w < WGM * WGN; ++w) {
+      f += red_f[w];
+      mx = fmaxf(mx, red_m[w]);
+    }
+    a.part_f[a.slot_base + item_id] = f;
+    a.part_m[a.slot_base + item_id] = (double)mx;
+  }
+  }
   }  // items
 }
 
@@ -309,7 +480,7 @@ k_products_direct(const ProductArgs a) {
   for (int item_id = slot; item_id < a.n_items; item_id += gridDim.x) {
   const TileItem it = a.items[item_id];
   int sexp = 0;
-  if (!item_active(a, it, &sexp)) continue;
+  if (!item_active<false>(a, it, &sexp)) continue;
   (void)sexp;  // direct forms store S1 unscaled
 
   const int64_t ld = a.ld;
@@ -460,33 +631,35 @@ static hipError_t launch_one(K kernel, int threads, size_t lds_bytes, int wg_per
   return hipGetLastError();
 }
 
-template <typename T16, int BK, int WGM, int WGN, int SWZ, int STAGES>
+template <typename T16, int BK, int WGM, int WGN, int SWZ, int STAGES, bool FUSED>
 static hipError_t launch_split_cfg(const ProductArgs& a, hipStream_t s) {
   constexpr size_t lds = (size_t)STAGES * (4 * kSplitBM) * (BK / 8) * 16;
-  static_assert(lds <= 160 * 1024, "LDS of one CU");
-  return launch_one(k_products_split<T16, kSplitBM, BK, WGM, WGN, SWZ, STAGES>,
+  static_assert(lds <= 160 * 1024 - 256, "LDS of one CU");
+  return launch_one(k_products_split<T16, kSplitBM, BK, WGM, WGN, SWZ, STAGES, FUSED>,
                     WGM * WGN * kWave, lds, 1, a, s);
 }
 
-template <typename T16>
+template <typename T16, bool FUSED>
 static hipError_t launch_split(const ProductArgs& a, hipStream_t s) {
-  return launch_split_cfg<T16, kPanelK, kSplitWGM, kSplitWGN, 2, 2>(a, s);
+  return launch_split_cfg<T16, kPanelK, kSplitWGM, kSplitWGN, 2, 2, FUSED>(a, s);
 }
 
 template <typename T16>
 static hipError_t launch_split_small(const ProductArgs& a, hipStream_t s) {
   // 128 x 128 tiles, 4 waves of 64 x 64, two workgroups per CU
   constexpr size_t lds = (size_t)2 * (4 * 128) * (kPanelK / 8) * 16;
-  return launch_one(k_products_split<T16, 128, kPanelK, 2, 2, 2, 2>, 4 * kWave, lds, 2, a, s);
+  return launch_one(k_products_split<T16, 128, kPanelK, 2, 2, 2, 2, true>, 4 * kWave, lds, 2, a,
+                    s);
 }
 
-hipError_t launch_products_batch(dmpt_precision prec, int tile, const ProductArgs& a,
+hipError_t launch_products_fused(dmpt_precision prec, int tile, const ProductArgs& a,
                                  hipStream_t s) {
-  if (!a.probs) return hipErrorInvalidValue;
+  if (!a.probs || !a.part_f || !a.part_m || (tile != 128 && tile != 256))
+    return hipErrorInvalidValue;
   if (prec == DMPT_SPLIT_FP16)
-    return tile == 128 ? launch_split_small<_Float16>(a, s) : launch_split<_Float16>(a, s);
+    return tile == 128 ? launch_split_small<_Float16>(a, s) : launch_split<_Float16, true>(a, s);
   if (prec == DMPT_SPLIT_BF16)
-    return tile == 128 ? launch_split_small<__bf16>(a, s) : launch_split<__bf16>(a, s);
+    return tile == 128 ? launch_split_small<__bf16>(a, s) : launch_split<__bf16, true>(a, s);
   return hipErrorInvalidValue;
 }
 
@@ -496,9 +669,9 @@ hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_
     return hipErrorInvalidValue;
   switch (prec) {
     case DMPT_SPLIT_FP16:
-      return launch_split<_Float16>(a, s);
+      return launch_split<_Float16, false>(a, s);
     case DMPT_SPLIT_BF16:
-      return launch_split<__bf16>(a, s);
+      return launch_split<__bf16, false>(a, s);
     case DMPT_FP32: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK32 / 4) * 16;
       return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN, kDirSWZ>,
@@ -511,6 +684,75 @@ hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_
     }
   }
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ trace of X before the products
+// One wave per 32 x 32 diagonal fragment of X = S^2: the same operand chunks,
+// k order and MFMA sequence per 16-wide k step as k_products_split (for a
+// diagonal fragment the A and B rows coincide), so the diagonal equals the
+// product's bitwise.  Output element (row, col) of lane l sits in column
+// l % 32 and row 8 (r / 4) + 4 (l / 32) + r % 4.
+template <typename T16>
+__global__ void __launch_bounds__(kWave) k_trace_diag(const ProblemDesc* probs,
+                                                     const TraceBlock* blocks, double* part) {
+  using S = Split16<T16>;
+  using V = typename S::V;
+  const TraceBlock tb = blocks[blockIdx.x];
+  const ProblemDesc& d = probs[tb.prob];
+  const LayerState* st = d.state;
+  if (st->done || st->d0) return;
+  const int lane = threadIdx.x;
+  const int par = st->s_par;
+  const uint16_t* hi = (const uint16_t*)d.s_hi[par];
+  const uint16_t* lo = (const uint16_t*)d.s_lo[par];
+  const int64_t row = (int64_t)tb.blk * 32 + (lane & 31);
+  const int64_t base = panel_index(row, 0, d.pdim) + 8 * (lane >> 5);
+  const int64_t kb = d.kdim / kPanelK;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll 4
+  for (int64_t b = 0; b < kb; ++b) {
+    const int64_t off = base + b * (kPanelRows * kPanelK);
+#pragma unroll
+    for (int kk = 0; kk < kPanelK / 16; ++kk) {
+      const V ah = *(const V*)(hi + off + 16 * kk);
+      const V al = *(const V*)(lo + off + 16 * kk);
+      acc = S::mma(S::up(ah), ah, acc);
+      acc = S::mma(ah, al, acc);
+      acc = S::mma(al, ah, acc);
+    }
+  }
+  // lane (c, h) holds the diagonal element of column c when h = (c / 4) % 2
+  const int c = lane & 31;
+  const float scale = ldexpf(1.0f, -S::kShift);
+  double v = 0.0;
+  if ((lane >> 5) == ((c >> 2) & 1) && tb.blk * 32 + c < st->n_real) {
+    const int ri = 4 * (c >> 3) + (c & 3);
+    float x = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      if (r == ri) x = acc[r] * scale;
+    v = (double)x;
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) part[blockIdx.x] = v;
+}
+
+hipError_t launch_trace_diag(dmpt_precision prec, const ProblemDesc* probs,
+                             const TraceBlock* blocks, int n_blocks, double* part, hipStream_t s) {
+  static_assert(kPanelK % 16 == 0, "k-steps of the split MFMA inside a panel block");
+  if (n_blocks <= 0) return hipSuccess;
+  if (prec == DMPT_SPLIT_FP16)
+    hipLaunchKernelGGL(k_trace_diag<_Float16>, dim3(n_blocks), dim3(kWave), 0, s, probs, blocks,
+                       part);
+  else if (prec == DMPT_SPLIT_BF16)
+    hipLaunchKernelGGL(k_trace_diag<__bf16>, dim3(n_blocks), dim3(kWave), 0, s, probs, blocks,
+                       part);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ MFMA layout self-test

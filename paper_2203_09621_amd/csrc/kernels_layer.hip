@@ -268,6 +268,7 @@ __global__ void k_reset_state(LayerState* st, int k, int max_layers, double nocc
   st->upd_s0 = 0;
   st->d0_now = 0;
   st->sigma_cur = 0;
+  st->s_par = 0;
   st->n_s = st->n_s0;
   st->fro0 = 0.0;
   for (int i = 0; i <= kMaxLayers; ++i) {
@@ -371,6 +372,30 @@ __global__ void __launch_bounds__(kBlk) k_decide1(LayerState* st, const double* 
 hipError_t launch_decide1(LayerState* st, const double* pfro0, const double* pfro1,
                           const double* pmax1, int split, int lo_shift, hipStream_t s) {
   hipLaunchKernelGGL(k_decide1, dim3(1), dim3(kBlk), 0, s, st, pfro0, pfro1, pmax1, split, lo_shift);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fused split layer
+__global__ void __launch_bounds__(kBlk) k_predecide(LayerState* st, const double* part, int np) {
+  predecide_body(st, part, np);
+}
+
+hipError_t launch_predecide(LayerState* st, const double* part, int np, hipStream_t s) {
+  hipLaunchKernelGGL(k_predecide, dim3(1), dim3(kBlk), 0, s, st, part, np);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlk) k_postdecide(LayerState* st, const TileItem* items,
+                                                    int n_items, const double* part_f,
+                                                    const double* part_m, int lo_shift) {
+  postdecide_body(st, items, n_items, part_f, part_m, lo_shift);
+}
+
+hipError_t launch_postdecide(LayerState* st, const TileItem* items, int n_items,
+                             const double* part_f, const double* part_m, int lo_shift,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_postdecide, dim3(1), dim3(kBlk), 0, s, st, items, n_items, part_f, part_m,
+                     lo_shift);
   return hipGetLastError();
 }
 

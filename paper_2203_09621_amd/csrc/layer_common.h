@@ -93,21 +93,11 @@ static __device__ __forceinline__ void split_one(float v, int e, int t, uint16_t
 
 
 // ------------------------------------------------------------------ decisions, part 1
-// Algorithm 1 trace test and Algorithm 2: N_X = Tr X in FP64, IdErr, sigma,
-// the D0 test and the N_S update.  After D0 converged: sigma flips.
-template <typename M>
-static __device__ void decide0_body(LayerState* st, const M* x, int64_t ld) {
-  const int done = st->done;
-  if (done) return;
+// Algorithm 1 trace test and Algorithm 2 for layer n = st->n + 1, given
+// N_X = Tr X_n (thread 0 only): IdErr, sigma, the D0 test and the N_S update.
+// After D0 converged: sigma flips.
+static __device__ void decide0_apply(LayerState* st, double nx) {
   const int d0 = st->d0;
-  const int n_real = st->n_real;
-  double nx = 0.0;
-  if (!d0) {
-    for (int i = threadIdx.x; i < n_real; i += kBlk) nx += (double)x[(int64_t)i * ld + i];
-    nx = block_sum(nx);
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
   const int n = st->n + 1;
   st->n = n;
   int sig;
@@ -147,6 +137,33 @@ static __device__ void decide0_body(LayerState* st, const M* x, int64_t ld) {
   st->sigma_cur = sig;
 }
 
+// After the products of layer n: N_X = Tr X in FP64 from the diagonal of X.
+template <typename M>
+static __device__ void decide0_body(LayerState* st, const M* x, int64_t ld) {
+  if (st->done) return;
+  const int d0 = st->d0;
+  const int n_real = st->n_real;
+  double nx = 0.0;
+  if (!d0) {
+    for (int i = threadIdx.x; i < n_real; i += kBlk) nx += (double)x[(int64_t)i * ld + i];
+    nx = block_sum(nx);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) decide0_apply(st, nx);
+}
+
+// Fused split layer, before the products of layer n: N_X = Tr X_n from the
+// diagonal-block partial sums part[0..np), then Algorithms 1-2.
+static __device__ void predecide_body(LayerState* st, const double* part, int np) {
+  if (st->done) return;
+  double nx = 0.0;
+  if (!st->d0) {
+    for (int i = threadIdx.x; i < np; i += kBlk) nx += part[i];
+    nx = block_sum(nx);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) decide0_apply(st, nx);
+}
 
 // ------------------------------------------------------------------ fused layer update
 // Thread range [q0 + tid*1, q1) with stride qs over float4/double4 vectors;
@@ -223,6 +240,53 @@ struct Partials {
   int n1[kMaxK];
 };
 
+// Algorithm 2 FroErr^(0) at the D0 layer and, per active response, Algorithm
+// 3 (thread 0 only): FroErr^(1)_n, the parameter-free D1 test (Eq. ConvCrit,
+// C_pt = 9), the next split scale, and the stop flag.  f0sq = ||S - X||_F^2
+// (used at the D0 layer), f1sq[j] = ||S1_j - X1_j||_F^2, m1[j] = max|S1_j,n|.
+static __device__ void decide1_apply(LayerState* st, double f0sq, const double* f1sq,
+                                     const double* m1, int split, int lo_shift) {
+  const int k = st->k;
+  const int d0 = st->d0;
+  const int n = st->n;
+  if (st->d0_now) {
+    st->fro0 = sqrt(f0sq);
+    if (!isfinite(st->fro0)) st->error = DMPT_ENONFINITE;
+  }
+  int all = 1;
+  for (int j = 0; j < k; ++j) {
+    if (st->d1[j]) continue;
+    const double mx = m1[j];
+    // the split written this layer used s1_exp_next; check it stayed in range
+    if (split && ldexp(mx, st->s1_exp_next[j] + lo_shift) > 32768.0) st->error = DMPT_ENONFINITE;
+    if (!isfinite(mx)) st->error = DMPT_ENONFINITE;
+    if (d0) {
+      const double f = sqrt(f1sq[j]);
+      st->fro1[j][n] = f;
+      if (!isfinite(f)) st->error = DMPT_ENONFINITE;
+      if (n - 2 >= st->d0_layer) {
+        const double prev = st->fro1[j][n - 2];
+        if (f > 9.0 * st->fro0 * prev || f == 0.0) {
+          st->d1[j] = 1;
+          st->d1_layer[j] = n;
+        }
+      }
+    }
+    st->s1_exp_hist[j][n] = st->s1_exp_next[j];   // the scale S1_n was just split with
+    st->s1_exp_split[j] = st->s1_exp_next[j];
+    st->s1_exp_next[j] = split_exponent(mx);
+    st->s1_max[j] = mx;
+    if (!st->d1[j]) all = 0;
+  }
+  if (all) {
+    st->converged = 1;
+    st->done = 1;
+  } else if (n >= st->max_layers) {
+    st->done = 1;
+  }
+  if (st->error) st->done = 1;
+}
+
 static __device__ void decide1_body(LayerState* st, const Partials& pr, int split, int lo_shift) {
   if (st->done) return;
   const int k = st->k;
@@ -251,43 +315,82 @@ static __device__ void decide1_body(LayerState* st, const Partials& pr, int spli
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const int n = st->n;
-  if (d0_now) {
-    st->fro0 = sqrt(res[2 * kMaxK]);
-    if (!isfinite(st->fro0)) st->error = DMPT_ENONFINITE;
+  double f1[kMaxK], m1[kMaxK];
+  for (int j = 0; j < kMaxK; ++j) {
+    f1[j] = j < k ? res[2 * j] : 0.0;
+    m1[j] = j < k ? res[2 * j + 1] : 0.0;
   }
-  int all = 1;
-  for (int j = 0; j < k; ++j) {
-    if (st->d1[j]) continue;
-    const double mx = res[2 * j + 1];
-    // the split written this layer used s1_exp_next; check it stayed in range
-    if (split && ldexp(mx, st->s1_exp_next[j] + lo_shift) > 32768.0) st->error = DMPT_ENONFINITE;
-    if (!isfinite(mx)) st->error = DMPT_ENONFINITE;
-    if (d0) {
-      const double f = sqrt(res[2 * j]);
-      st->fro1[j][n] = f;
-      if (!isfinite(f)) st->error = DMPT_ENONFINITE;
-      if (n - 2 >= st->d0_layer) {
-        const double prev = st->fro1[j][n - 2];
-        if (f > 9.0 * st->fro0 * prev || f == 0.0) {
-          st->d1[j] = 1;
-          st->d1_layer[j] = n;
-        }
-      }
+  decide1_apply(st, d0_now ? res[2 * kMaxK] : 0.0, f1, m1, split, lo_shift);
+}
+
+// Fused split layer, after the products of layer n: the per-item partials of
+// this problem's items (slots part + index) are combined in a fixed order.
+// Output 0 carries ||S - X||_F^2 at the D0 layer; output 1 + j carries
+// ||S1_j - X1_j||_F^2 (after D0) and max|S1_j,n|.  Outputs skipped this layer
+// are ignored.
+static __device__ void postdecide_body(LayerState* st, const TileItem* items, int n_items,
+                                       const double* part_f, const double* part_m, int lo_shift) {
+  if (st->done) return;
+  const int k = st->k;
+  const int xc = st->x_computed;
+  int act[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) act[j] = j < k && !st->d1[j];
+  double f[kMaxK + 1], m[kMaxK];
+#pragma unroll
+  for (int q = 0; q <= kMaxK; ++q) f[q] = 0.0;
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) m[j] = 0.0;
+  for (int i = threadIdx.x; i < n_items; i += kBlk) {
+    const int o = items[i].out;
+    const double pf = part_f[i];
+    if (o == 0) {
+      if (xc) f[0] += pf;
+      continue;
     }
-    st->s1_exp_hist[j][n] = st->s1_exp_next[j];   // the scale S1_n was just split with
-    st->s1_exp_split[j] = st->s1_exp_next[j];
-    st->s1_exp_next[j] = split_exponent(mx);
-    st->s1_max[j] = mx;
-    if (!st->d1[j]) all = 0;
+    const double pm = part_m[i];
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j)
+      if (o == 1 + j && act[j]) {
+        f[1 + j] += pf;
+        m[j] = fmax(m[j], pm);
+      }
   }
-  if (all) {
-    st->converged = 1;
-    st->done = 1;
-  } else if (n >= st->max_layers) {
-    st->done = 1;
+  __shared__ double res[2 * kMaxK + 1];
+  {
+    const double v = block_sum(f[0]);
+    if (threadIdx.x == 0) res[2 * kMaxK] = v;
   }
-  if (st->error) st->done = 1;
+  for (int j = 0; j < k; ++j) {
+    double v = 0.0, w = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxK; ++q)
+      if (q == j) {
+        v = f[1 + q];
+        w = m[q];
+      }
+    v = block_sum(v);
+    w = block_max(w);
+    if (threadIdx.x == 0) {
+      res[2 * j] = v;
+      res[2 * j + 1] = w;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double f0sq = 0.0;
+  if (xc) {
+    if (st->upd_s0)
+      st->s_par ^= 1;          // the epilogue wrote the split of S_n to the other buffer
+    else
+      f0sq = res[2 * kMaxK];
+  }
+  double f1[kMaxK], m1[kMaxK];
+  for (int j = 0; j < kMaxK; ++j) {
+    f1[j] = j < k ? res[2 * j] : 0.0;
+    m1[j] = j < k ? res[2 * j + 1] : 0.0;
+  }
+  decide1_apply(st, f0sq, f1, m1, 1, lo_shift);
 }
 
 

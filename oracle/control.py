@@ -14,6 +14,14 @@ Readings where the pseudocode is silent or garbled (listed in the design notes):
   * N_S <- sigma N_X + (1 - sigma) N_S, tracked as a scalar.
   * several perturbations share one S^(0) chain; each keeps its own FroErr^(1)
     history and stop flag; a stopped response is frozen.
+  * second order (the paper gives stopping tests for first order only): the
+    response S^(2) of the first perturbation is updated every layer until its
+    own test fires.  The test is Alg. 3 applied to FroErr^(2)_n =
+    ||S^(2)_{n-1} - X^(2)_n||_F, started two layers after the D1 layer of that
+    perturbation: with S^(0) and S^(1) frozen, the S^(2) map has the same
+    linear part as the S^(1) map with S^(0) frozen (Eq. S_n detailed with k = 2
+    minus k = 1), so the same C_pt applies.  It also fires on an exact zero;
+    the result is S^(2)_{n-1}.
 Constants: C_pt = 9 (Sec. IV, valid on [-0.25, 1.25]); the 4.5 factor of the
 D0 test comes from earlier work (parity unpinned).
 """
@@ -24,7 +32,8 @@ D0_FACTOR = 4.5
 
 
 class SP2PTControl:
-    def __init__(self, nocc: float, n_s: float, k: int, max_layers: int = 100):
+    def __init__(self, nocc: float, n_s: float, k: int, max_layers: int = 100,
+                 order2: bool = False):
         self.nocc = float(nocc)
         self.n_s = float(n_s)
         self.k = int(k)
@@ -38,6 +47,10 @@ class SP2PTControl:
         self.fro1 = [dict() for _ in range(self.k)]
         self.d1 = [False] * self.k
         self.d1_layer = [None] * self.k
+        self.order2 = bool(order2)
+        self.fro2: dict = {}
+        self.d2 = False
+        self.d2_layer = None
 
     # ---------------------------------------------------------------- layers
     def begin_layer(self) -> int:
@@ -92,8 +105,25 @@ class SP2PTControl:
                 return False
         return True
 
+    def second_order(self, fro2) -> bool:
+        """The second-order test (design reading above) for the response of
+        the first perturbation.  ``fro2`` gives ||S2_{n-1} - X2_n||_F.
+        Returns whether S2 is updated this layer."""
+        if self.d2:
+            return False
+        if self.d0:
+            f = float(fro2())
+            self.fro2[self.n] = f
+            if self.d1[0] and self.n - 2 >= self.d1_layer[0]:
+                prev = self.fro2.get(self.n - 2)
+                if prev is not None and (f > C_PT * self.fro0 * prev or f == 0.0):
+                    self.d2 = True
+                    self.d2_layer = self.n
+                    return False
+        return True
+
     def done(self) -> bool:
-        return all(self.d1)
+        return all(self.d1) and (self.d2 or not self.order2)
 
     def exhausted(self) -> bool:
         return self.n >= self.max_layers
@@ -107,5 +137,7 @@ class SP2PTControl:
             "iderr": list(self.iderr),
             "fro0": self.fro0,
             "fro1": [dict(f) for f in self.fro1],
+            "d2_layer": self.d2_layer,
+            "fro2": dict(self.fro2),
             "converged": self.done(),
         }

@@ -11,6 +11,20 @@ occupied and a virtual, zero inside the occupied and the virtual blocks.  This
 is the sum-over-states form
     P1 = sum_{i occ, a virt} (v_i v_a^T + v_a v_i^T) (v_a^T H1 v_i)/(e_i - e_a).
 
+P2 is the second-order coefficient of P(H0 + lambda H1 + lambda^2 H2) (Sec. III,
+the lambda^2 term of the density-matrix expansion).  The second-order
+Daleckii-Krein form in the eigenbasis (tilde = V^T . V) is
+    P2~_ij = sum_k theta[e_i, e_k, e_j] H1~_ik H1~_kj + theta[e_i, e_j] H2~_ij
+with the second divided differences of the step: theta[o, o', a] =
+-1/((e_o - e_a)(e_o' - e_a)) and theta[o, a, b] = 1/((e_o - e_a)(e_o - e_b)) for
+o, o' occupied and a, b virtual, zero when all three levels share a side.
+With C = D o H1~_vo, D_ao = 1/(e_o - e_a) (so P1~_vo = C), the blocks are
+    P2~_oo = -C^T C,   P2~_vv = C C^T,   P2~_vo = D o (H1~_vv C - C H1~_oo + H2~_vo).
+Pins (tests/test_oracle_second.py): second differences of P(H0 + h H1 + h^2 H2)
+with the Newton-sign P, first differences of P1, the explicit triple sum with a
+generic divided difference on small inputs, the 2x2 closed form, and the
+second-order blocks of D^2 = D and HD = DH.
+
 Pins (tests/test_oracle_exact.py): brute-force finite differences of P(H0 +
 lambda H1) (Eqs. FnD_2/FnD_4) with P computed by a Newton sign iteration that
 never calls eigh; the 2x2 closed form; the diagonal-H0 case; the invariants
@@ -104,6 +118,45 @@ def solve_from_factors(e: np.ndarray, q: np.ndarray, h1s, nocc: int):
     v = q[:, order]
     vo = v[:, :nocc]
     return vo @ vo.T, [response_from_eigs(es, v, h, nocc) for h in h1s]
+
+
+def second_order_from_eigs(e: np.ndarray, v: np.ndarray, h1: np.ndarray, h2, nocc: int):
+    """P2 from eigenpairs sorted ascending (h2 may be None: no second-order term
+    in the Hamiltonian)."""
+    vo, vv = v[:, :nocc], v[:, nocc:]
+    d = 1.0 / (e[None, :nocc] - e[nocc:, None])          # D_ao = 1/(e_o - e_a)
+    t_vo = vv.T @ (h1 @ vo)
+    t_oo = vo.T @ (h1 @ vo)
+    t_vv = vv.T @ (h1 @ vv)
+    c = d * t_vo
+    p_oo = -(c.T @ c)
+    p_vv = c @ c.T
+    inner = t_vv @ c - c @ t_oo
+    if h2 is not None:
+        inner = inner + vv.T @ (h2 @ vo)
+    p_vo = d * inner
+    m = vv @ (p_vo @ vo.T)
+    return vo @ (p_oo @ vo.T) + vv @ (p_vv @ vv.T) + m + m.T
+
+
+def second_order_response(h0: np.ndarray, h1: np.ndarray, h2, nocc: int):
+    """(P0, P1, P2) of H(lambda) = H0 + lambda H1 + lambda^2 H2."""
+    e, v = eigensystem(h0)
+    check_gap(e, nocc)
+    vo = v[:, :nocc]
+    p1 = response_from_eigs(e, v, h1, nocc)   # H2 enters at second order only
+    return vo @ vo.T, p1, second_order_from_eigs(e, v, h1, h2, nocc)
+
+
+def invariants2(h0, h1, h2, p0, p1, p2) -> dict:
+    """Second-order blocks of D^2 = D and HD = DH, and Tr P2 (= 0: the
+    occupation does not depend on lambda)."""
+    h2 = np.zeros_like(h0) if h2 is None else h2
+    return {
+        "tr_p2": float(np.trace(p2)),
+        "idem2": float(np.linalg.norm(p0 @ p2 + p1 @ p1 + p2 @ p0 - p2)),
+        "comm2": float(np.linalg.norm(h0 @ p2 - p2 @ h0 + h1 @ p1 - p1 @ h1 + h2 @ p0 - p0 @ h2)),
+    }
 
 
 def _apply_layers(m, layers, offsets, block, transpose: bool):

@@ -6,8 +6,12 @@ Deep layer n (Eq. S_n detailed with the bias of Eq. dB):
     X_n   = S_{n-1}^2,                       S_n   = sigma_n X_n   + (1 - sigma_n) S_{n-1}
     X1_n  = S_{n-1} S1_{n-1} + S1_{n-1} S_{n-1},
     S1_n  = sigma_n X1_n + (1 - sigma_n) S1_{n-1}
-with sigma_n and the stopping tests from ``control``.  Plain numpy matmuls, no
-symmetry tricks, no reordering.
+with sigma_n and the stopping tests from ``control``.  With ``order2`` the
+second-order response of the first perturbation follows the k = 2 case of
+Eq. S_n detailed,
+    X2_n  = S_{n-1} S2_{n-1} + S1_{n-1} S1_{n-1} + S2_{n-1} S_{n-1},
+    S2_n  = sigma_n X2_n + (1 - sigma_n) S2_{n-1},   S2_0 = -H2/(eps_N - eps_1).
+Plain numpy matmuls, no symmetry tricks, no reordering.
 
 Pins: its converged output equals ``exact`` to the FP64 level, and its
 per-layer matrices equal those of ``eigsim`` (an independent eigenbasis
@@ -30,15 +34,20 @@ def initial_layer(h0, h1s):
     return s0, s1, (e1, en)
 
 
-def run(h0: np.ndarray, h1s, nocc: int, max_layers: int = 100, record: bool = False):
-    """Returns (P0, [P1_k], stats).  ``stats['converged']`` is False when the
-    layer cap was reached first."""
+def run(h0: np.ndarray, h1s, nocc: int, max_layers: int = 100, record: bool = False,
+        order2: bool = False, h2=None):
+    """Returns (P0, [P1_k], stats), plus stats['p2'] with ``order2``.
+    ``stats['converged']`` is False when the layer cap was reached first."""
     s0, s1, bounds = initial_layer(h0, h1s)
-    ctl = SP2PTControl(nocc, float(np.trace(s0)), len(s1), max_layers)
+    ctl = SP2PTControl(nocc, float(np.trace(s0)), len(s1), max_layers, order2=order2)
+    s2 = None
+    if order2:
+        s2 = np.zeros_like(h0) if h2 is None else -h2 / (bounds[1] - bounds[0])
     hist = [] if record else None
     while not ctl.done() and not ctl.exhausted():
         ctl.begin_layer()
         x1 = [None if ctl.d1[j] else s0 @ s + s @ s0 for j, s in enumerate(s1)]
+        x2 = None if (s2 is None or ctl.d2) else s0 @ s2 + s1[0] @ s1[0] + s2 @ s0
         if not ctl.d0:
             x0 = s0 @ s0
             sig, upd = ctl.zeroth_order(np.trace(x0), lambda: np.linalg.norm(s0 - x0))
@@ -53,11 +62,15 @@ def run(h0: np.ndarray, h1s, nocc: int, max_layers: int = 100, record: bool = Fa
                 continue
             if ctl.first_order(j, lambda: np.linalg.norm(s1[j] - x1[j])):
                 s1[j] = sig * x1[j] + (1 - sig) * s1[j]
+        if x2 is not None and ctl.second_order(lambda: np.linalg.norm(s2 - x2)):
+            s2 = sig * x2 + (1 - sig) * s2
         del s0_prev
         if record:
             hist.append((s0.copy(), [s.copy() for s in s1]))
     st = ctl.stats()
     st["eps1"], st["epsN"] = bounds
+    if order2:
+        st["p2"] = s2
     if record:
         st["history"] = hist
     return s0, s1, st

@@ -122,6 +122,20 @@ dmpt_status dmpt_set_hamiltonian(dmpt_ctx* ctx, const double* H0);
 dmpt_status dmpt_response(dmpt_ctx* ctx, const double* const* H1, int32_t k, double* P0,
                           double* const* P1, dmpt_stats* st);
 
+/* Second-order response (Sec. III, Eq. S_n detailed with k = 2): for
+ * H(lambda) = H0 + lambda H1 + lambda^2 H2, returns P0, P1 = D^(1) and
+ * P2 = D^(2), the lambda^2 coefficient of the density matrix.  The chain
+ * S2_n = sigma_n (S S2 + S1 S1 + S2 S) + (1 - sigma_n) S2, S2_0 = -H2/(eps_N -
+ * eps_1), runs in the second response slot of the context, so the context needs
+ * k_max >= 2.  H2 may be NULL (no second-order term in H).  The paper gives
+ * stopping tests for first order only; S2 takes Algorithm 3's test on
+ * ||S2 - X2||_F from two layers after the D1 layer on, and P2 is S2 of the
+ * layer before that test fired.  In `st`, index 1 of d1_layer, idem1 and
+ * trace_p1 refers to P2.  P0 may be NULL.  Errors as dmpt_response; the
+ * adjoint does not cover this form. */
+dmpt_status dmpt_response2(dmpt_ctx* ctx, const double* H1, const double* H2, double* P0,
+                           double* P1, double* P2, dmpt_stats* st);
+
 /* Reverse mode of the layer recursion for L = sum_j Tr(P1_j W_j), applied to
  * the most recent successful dmpt_response of this context (same k, k <= 3;
  * the context needs ckpt_every > 0).  W[j] (host array of device FP64 N x N)

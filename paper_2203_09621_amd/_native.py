@@ -22,6 +22,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
+           "dmpt_response2",
            "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
            "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
@@ -90,6 +91,9 @@ def _load():
     lib.dmpt_response.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
                                   POINTER(c_void_p), POINTER(DmptStats)]
     lib.dmpt_response.restype = c_int32
+    lib.dmpt_response2.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   POINTER(DmptStats)]
+    lib.dmpt_response2.restype = c_int32
     lib.dmpt_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
                                  POINTER(c_void_p), POINTER(DmptStats)]
     lib.dmpt_adjoint.restype = c_int32
@@ -200,6 +204,23 @@ def dmpt_response(ctx: c_void_p, H1s, P0=None, P1s=None):
     _check(status, stats)
     del n
     return P0, P1s, stats
+
+
+def dmpt_response2(ctx: c_void_p, H1, H2=None, P0=None, P1=None, P2=None):
+    """dmpt_response2: P0, P1 and the second-order P2 of H0 + l H1 + l^2 H2
+    (H2 may be None).  The context needs k_max >= 2.  Returns (P0, P1, P2,
+    stats); stats index 1 of d1_layer / idem1 / trace_p1 refers to P2."""
+    torch = _torch()
+    P0 = torch.empty_like(H1) if P0 is None else P0
+    P1 = torch.empty_like(H1) if P1 is None else P1
+    P2 = torch.empty_like(H1) if P2 is None else P2
+    h2 = _dev(H2, "H2") if H2 is not None else c_void_p(None)
+    st = DmptStats()
+    status = LIB.dmpt_response2(ctx, _dev(H1, "H1"), h2, _dev(P0, "P0"), _dev(P1, "P1"),
+                                _dev(P2, "P2"), byref(st))
+    stats = st.as_dict()
+    _check(status, stats)
+    return P0, P1, P2, stats
 
 
 def dmpt_adjoint(ctx: c_void_p, Ws, dH0=None, dH1s=None):

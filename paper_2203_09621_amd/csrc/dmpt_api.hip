@@ -411,17 +411,24 @@ dmpt_status dmpt_set_hamiltonian(dmpt_ctx* c, const double* H0) {
 
 void dmpt_destroy(dmpt_ctx* ctx) { ctx_free(ctx); }
 
-dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, double* P0,
-                          double* const* P1, dmpt_stats* stats) {
-  if (!c) return fail(DMPT_EINVAL, "ctx is NULL");
-  if (k < 1 || k > c->k_max) return fail(DMPT_EINVAL, "k out of [1, k_max]");
-  if (!H1 || !P1) return fail(DMPT_EINVAL, "H1 / P1 array is NULL");
-  for (int j = 0; j < k; ++j)
-    if (!H1[j] || !P1[j]) return fail(DMPT_EINVAL, "NULL H1[j] or P1[j]");
+}  // extern "C"
+
+namespace {
+
+// The layer loop of Algorithm 1 for k1 first-order responses and, with order2,
+// the second-order chain of the first perturbation in response slot k1
+// (initial matrix -H2/(eps_N - eps_1), zero when H2 is NULL; result into P2).
+dmpt_status run_response(dmpt_ctx* c, const double* const* H1, int k1, bool order2,
+                         const double* H2, double* P0, double* const* P1, double* P2,
+                         dmpt_stats* stats) {
+  const int k = k1 + (order2 ? 1 : 0);   // response slots
+  auto slot_in = [&](int j) -> const double* { return j < k1 ? H1[j] : H2; };
+  auto slot_out = [&](int j) -> double* { return j < k1 ? P1[j] : P2; };
   hipStream_t s = c->stream;
   if (c->check_sym)
     for (int j = 0; j < k; ++j) {
-      dmpt_status r = check_symmetric(H1[j], c->n, c->dflag, c->hflag, s, "H1");
+      if (!slot_in(j)) continue;
+      dmpt_status r = check_symmetric(slot_in(j), c->n, c->dflag, c->hflag, s, "H1");
       if (r != DMPT_OK) return r;
     }
   const dmpt_precision prec = c->prec;
@@ -430,10 +437,10 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
   const int64_t ld = c->ld, np = c->np, elems = np * ld;
 
   HIPCHK(hipEventRecord(c->ev0, s));
-  HIPCHK(launch_reset_state(c->st, k, c->max_layers, (double)c->nocc, c->n, s));
+  HIPCHK(launch_reset_state(c->st, k, order2 ? k1 : -1, c->max_layers, (double)c->nocc, c->n, s));
   HIPCHK(launch_load_s0(prec, c->s_init, c->s_master, c->s_hi[0], c->s_lo[0], np, ld, t, s));
   for (int j = 0; j < k; ++j)
-    HIPCHK(launch_init_s1(prec, H1[j], c->n, np, ld, c->st, j, c->part + kPartMaxabs,
+    HIPCHK(launch_init_s1(prec, slot_in(j), c->n, np, ld, c->st, j, c->part + kPartMaxabs,
                           c->s1buf[j][0], c->s1_hi[j][0], c->s1_lo[j][0], t, 0.0, s));
 
   const size_t mbytes = (size_t)elems * elem_bytes(prec);
@@ -466,6 +473,8 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
     pa.state = c->st;
     pa.ld = ld;
     pa.kdim = np;
+    pa.s1b[0] = c->s1buf[0][0];
+    pa.s1b[1] = c->s1buf[0][1];
   }
 
   int n = 0;
@@ -508,10 +517,11 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
   }
   if (P0) HIPCHK(launch_copy_out(prec, c->st, -1, c->s_master, c->s_master, ld, P0, c->n, s));
   for (int j = 0; j < k; ++j)
-    HIPCHK(launch_copy_out(prec, c->st, j, c->s1buf[j][0], c->s1buf[j][1], ld, P1[j], c->n, s));
+    HIPCHK(launch_copy_out(prec, c->st, j, c->s1buf[j][0], c->s1buf[j][1], ld, slot_out(j), c->n,
+                           s));
   HIPCHK(hipEventRecord(c->ev1, s));
   if (P0) HIPCHK(launch_trace(P0, c->n, c->dscal, s));
-  for (int j = 0; j < k; ++j) HIPCHK(launch_trace(P1[j], c->n, c->dscal + 1 + j, s));
+  for (int j = 0; j < k; ++j) HIPCHK(launch_trace(slot_out(j), c->n, c->dscal + 1 + j, s));
   HIPCHK(hipMemcpyAsync(c->hstate, c->st, sizeof(LayerState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->hscal, c->dscal, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -551,8 +561,32 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
   }
   if (h.error) return fail((dmpt_status)h.error, "non-finite value or split overflow in a layer");
   if (!h.converged) return fail(DMPT_ENOCONV, "layer cap reached before every D1 test fired");
-  c->last_k = k;
+  c->last_k = order2 ? 0 : k;          // the adjoint covers first-order responses
   return DMPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, double* P0,
+                          double* const* P1, dmpt_stats* stats) {
+  if (!c) return fail(DMPT_EINVAL, "ctx is NULL");
+  if (k < 1 || k > c->k_max) return fail(DMPT_EINVAL, "k out of [1, k_max]");
+  if (!H1 || !P1) return fail(DMPT_EINVAL, "H1 / P1 array is NULL");
+  for (int j = 0; j < k; ++j)
+    if (!H1[j] || !P1[j]) return fail(DMPT_EINVAL, "NULL H1[j] or P1[j]");
+  return run_response(c, H1, k, false, nullptr, P0, P1, nullptr, stats);
+}
+
+dmpt_status dmpt_response2(dmpt_ctx* c, const double* H1, const double* H2, double* P0,
+                           double* P1, double* P2, dmpt_stats* stats) {
+  if (!c) return fail(DMPT_EINVAL, "ctx is NULL");
+  if (c->k_max < 2) return fail(DMPT_EINVAL, "second order needs a context with k_max >= 2");
+  if (!H1 || !P1 || !P2) return fail(DMPT_EINVAL, "NULL H1, P1 or P2");
+  const double* h1[1] = {H1};
+  double* p1[1] = {P1};
+  return run_response(c, h1, 1, true, H2, P0, p1, P2, stats);
 }
 
 dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double* dH0,

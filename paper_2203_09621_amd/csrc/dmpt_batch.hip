@@ -87,6 +87,7 @@ __global__ void __launch_bounds__(kBlk) k_b_setup(BatchProblem* P, const double*
   const double w = hi - lo;
   st->n_real = (int32_t)n;
   st->k = b.k;
+  st->order2_slot = -1;
   st->max_layers = max_layers;
   st->nocc = b.nocc;
   st->eps1 = lo;

@@ -64,7 +64,7 @@ struct LayerState {
   int32_t d0_now;            // the D0 test fired at layer n
   int32_t sigma_cur;         // sigma_n
   int32_t s_par;             // fused split forms: buffer of the current 16-bit split of S
-  int32_t pad1;
+  int32_t order2_slot;       // response slot of the second-order chain S2 (-1: none)
   double n_s;                // tracked occupation N_S
   double n_s0;               // Tr S0 of the normalisation layer
   double fro0;               // ||S - S^2||_F at the D0 layer
@@ -81,7 +81,8 @@ struct LayerState {
   int32_t s1_exp_hist[kMaxK][kMaxLayers + 1];   // split scale S1_n was written with
 };
 
-// One output tile of a layer product.  out = 0: X = S^2; out = 1 + j: X1_j.
+// One output tile of a layer product.  out = 0: X = S^2; out = 1 + j: X1_j,
+// or X2 = S1_0 S1_0 + S S2 + S2 S when j is the state's second-order slot.
 struct TileItem {
   int16_t out;
   int16_t prob;              // problem index (batched launches; 0 otherwise)
@@ -124,6 +125,7 @@ struct ProductArgs {
   void* x;                   // X (FP32 or FP64)
   void* x1[kMaxK];           // X1_j
   const void* a_op[kMaxK];    // direct forms: A operand of output 1 + j (NULL: S)
+  const void* s1b[2];        // direct forms: both buffers of S1_0 (second-order products)
   const ProblemDesc* probs;  // fused split layer: per-problem buffers (NULL: the fields here)
   double* part_f;            // fused: per-item FP64 sums (squares), slot slot_base + item
   double* part_m;            // fused: per-item max |S1_new|
@@ -169,8 +171,9 @@ hipError_t launch_load_s0(dmpt_precision prec, const void* s_init, void* master,
 hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int64_t rows,
                           int64_t ld, LayerState* st, int j, double* partial, void* s1, void* hi,
                           void* lo, int t, double w_fixed, hipStream_t s);
-hipError_t launch_reset_state(LayerState* st, int k, int max_layers, double nocc, int64_t n,
-                              hipStream_t s);
+// k response slots; order2_slot (-1: none) carries the second-order chain.
+hipError_t launch_reset_state(LayerState* st, int k, int order2_slot, int max_layers, double nocc,
+                              int64_t n, hipStream_t s);
 hipError_t launch_decide0(dmpt_precision prec, LayerState* st, const void* x, int64_t ld,
                           hipStream_t s);
 hipError_t launch_update(dmpt_precision prec, const LayerState* st, int which, const void* x,

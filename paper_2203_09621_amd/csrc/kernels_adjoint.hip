@@ -35,6 +35,7 @@ __global__ void k_replay_state(const LayerState* f, LayerState* r, int n) {
   if (threadIdx.x != 0) return;
   r->n = n;
   r->k = f->k;
+  r->order2_slot = -1;
   r->n_real = f->n_real;
   r->done = 0;
   r->error = 0;

@@ -131,28 +131,49 @@ k_products_split(const ProductArgs a) {
   if (!item_active<FUSED>(a, it, &sexp)) continue;
 
   const int j = it.out - 1;
-  const int nprod = it.out == 0 ? 1 : 2;
   // operands of this item: the problem's descriptor (fused) or the launch fields
   const ProblemDesc* pd = FUSED ? a.probs + it.prob : nullptr;
   const LayerState* fst = FUSED ? pd->state : nullptr;
   const int64_t ld = FUSED ? pd->ld : a.ld;
   const int64_t kdim = FUSED ? pd->kdim : a.kdim;
   const int64_t pdim = FUSED ? pd->pdim : a.kdim;
-  // operand panels per product: [hi_A, lo_A, hi_B, lo_B]
-  const uint16_t* P[2][4];
+  // second-order chain (fused only): X2 = S1_0 S1_0 + S S2 + S2 S
+  const bool second = FUSED && it.out > 0 && j == fst->order2_slot;
+  const int nprod = it.out == 0 ? 1 : (second ? 3 : 2);
+  // operand panels per product p: Q<p> = [hi_A, lo_A, hi_B, lo_B]
+  const uint16_t *Q0[4], *Q1[4], *Q2[4];
+  float rescale = 1.0f;      // second order: 2^(e2 - 2 e1) after the S1_0 S1_0 product
   {
     const int sp = FUSED ? fst->s_par : 0;
     const int lp = FUSED ? ((fst->n - 1) & 1) : 0;   // S1_{n-1} split
     const uint16_t* sh = (const uint16_t*)(FUSED ? pd->s_hi[sp] : a.s_hi);
     const uint16_t* sl = (const uint16_t*)(FUSED ? pd->s_lo[sp] : a.s_lo);
-    if (it.out == 0) {
-      P[0][0] = sh; P[0][1] = sl; P[0][2] = sh; P[0][3] = sl;
-      P[1][0] = sh; P[1][1] = sl; P[1][2] = sh; P[1][3] = sl;
+    const uint16_t* th = sh;
+    const uint16_t* tl = sl;
+    if (it.out != 0) {
+      th = (const uint16_t*)(FUSED ? pd->s1_hi[j][lp] : a.s1_hi[j]);
+      tl = (const uint16_t*)(FUSED ? pd->s1_lo[j][lp] : a.s1_lo[j]);
+    }
+    // X: S S;  X1_j: S S1_j, S1_j S;  X2: S1_0 S1_0, S S2, S2 S
+    const uint16_t* uh = sh;
+    const uint16_t* ul = sl;
+    if (second) {
+      // S1_0 frozen at its D1 result S1_{d1-1} once its test fired
+      const bool fz = fst->d1[0] != 0;
+      const int fp = fz ? ((fst->d1_layer[0] - 1) & 1) : lp;
+      const int e1 = fz ? fst->s1_exp_hist[0][fst->d1_layer[0] - 1] : fst->s1_exp_split[0];
+      uh = (const uint16_t*)pd->s1_hi[0][fp];
+      ul = (const uint16_t*)pd->s1_lo[0][fp];
+      rescale = ldexpf(1.0f, sexp - 2 * e1);
+    }
+    if (second) {
+      Q0[0] = uh; Q0[1] = ul; Q0[2] = uh; Q0[3] = ul;
+      Q1[0] = sh; Q1[1] = sl; Q1[2] = th; Q1[3] = tl;
+      Q2[0] = th; Q2[1] = tl; Q2[2] = sh; Q2[3] = sl;
     } else {
-      const uint16_t* th = (const uint16_t*)(FUSED ? pd->s1_hi[j][lp] : a.s1_hi[j]);
-      const uint16_t* tl = (const uint16_t*)(FUSED ? pd->s1_lo[j][lp] : a.s1_lo[j]);
-      P[0][0] = sh; P[0][1] = sl; P[0][2] = th; P[0][3] = tl;
-      P[1][0] = th; P[1][1] = tl; P[1][2] = sh; P[1][3] = sl;
+      Q0[0] = sh; Q0[1] = sl; Q0[2] = th; Q0[3] = tl;
+      Q1[0] = th; Q1[1] = tl; Q1[2] = sh; Q1[3] = sl;
+      Q2[0] = th; Q2[1] = tl; Q2[2] = sh; Q2[3] = sl;
     }
   }
   const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BN;
@@ -178,7 +199,7 @@ k_products_split(const ProductArgs a) {
       const int64_t row0 = arr < 2 ? row_a0 : row_b0;
       const int64_t soff = ((row0 / kPanelRows) * kblocks + kt) * (kPanelRows * kPanelK) +
                            (row0 % kPanelRows + (int64_t)(i * RPL - arr * BM)) * kPanelK;
-      const uint16_t* basep = (p == 0 ? P[0][arr] : P[1][arr]) + soff;
+      const uint16_t* basep = (p == 0 ? Q0[arr] : (p == 1 ? Q1[arr] : Q2[arr])) + soff;
       u32x4* dst = dst_stage + (i * RPL + wave * RPW) * CH;            // wave-uniform
       __builtin_amdgcn_global_load_lds((const void*)(basep + voff), (void*)dst, 16, 0, 0);
     }
@@ -239,6 +260,13 @@ k_products_split(const ProductArgs a) {
       for (int m = 0; m < FM; ++m)
 #pragma unroll
         for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(al[m], bh[n], acc[m][n]);
+    }
+    if (second && t == kt_per - 1) {
+      // S1_0 S1_0 done (scale 2^(t + 2 e1)): bring it to the scale of S S2
+#pragma unroll
+      for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] *= rescale;
     }
     // own loads of tile t+1 landed (tiles t+2 .. may stay in flight), then
     // everyone: tile t+1 readable, stage t % STAGES free for reuse
@@ -485,17 +513,29 @@ k_products_direct(const ProductArgs a) {
 
   const int64_t ld = a.ld;
   const int j = it.out - 1;
-  const int nprod = it.out == 0 ? 1 : 2;
-  // out 0: S S;  out 1 + j: A B + B A with A = a_op[j] (default S), B = s1_hi[j]
-  const T* P[2][2];
+  // the second-order chain: X2 = S1_0 S1_0 + S S2 + S2 S (S2 = s1_hi[j])
+  const bool second = it.out > 0 && a.state && j == a.state->order2_slot;
+  const int nprod = it.out == 0 ? 1 : (second ? 3 : 2);
+  // out 0: S S;  out 1 + j: A B + B A with A = a_op[j] (default S), B = s1_hi[j];
+  // X2: S1_0 S1_0, S S2, S2 S.  Operands of product p: [A rows, B rows].
+  const T *Q0[2], *Q1[2], *Q2[2];
   {
     const T* s = (const T*)a.s_hi;
-    if (it.out == 0) {
-      P[0][0] = s; P[0][1] = s; P[1][0] = s; P[1][1] = s;
+    const T* aa = s;
+    const T* bb = s;
+    if (it.out != 0) {
+      aa = a.a_op[j] ? (const T*)a.a_op[j] : s;
+      bb = (const T*)a.s1_hi[j];
+    }
+    if (second) {
+      // these products run before the layer's decisions: S1_{n-1} sits in
+      // buffer state->n & 1, or S1_0 is frozen at S1_{d1-1}
+      const LayerState* st = a.state;
+      const int fp = st->d1[0] ? ((st->d1_layer[0] - 1) & 1) : (st->n & 1);
+      const T* u = (const T*)a.s1b[fp];
+      Q0[0] = u; Q0[1] = u; Q1[0] = s; Q1[1] = bb; Q2[0] = bb; Q2[1] = s;
     } else {
-      const T* aa = a.a_op[j] ? (const T*)a.a_op[j] : s;
-      const T* bb = (const T*)a.s1_hi[j];
-      P[0][0] = aa; P[0][1] = bb; P[1][0] = bb; P[1][1] = aa;
+      Q0[0] = aa; Q0[1] = bb; Q1[0] = bb; Q1[1] = aa; Q2[0] = bb; Q2[1] = aa;
     }
   }
   const int tid = threadIdx.x;
@@ -516,7 +556,7 @@ k_products_direct(const ProductArgs a) {
       const int arr = (i * RPL) / BM;             // compile-time after unrolling
       const int r = i * RPL - arr * BM + lrow;
       const int64_t grow = (arr == 0 ? row_a0 : row_b0) + r;
-      const T* basep = p == 0 ? P[0][arr] : P[1][arr];
+      const T* basep = p == 0 ? Q0[arr] : (p == 1 ? Q1[arr] : Q2[arr]);
       regs[i] = *(const u32x4*)(basep + grow * ld + k0 + lch * E);
     }
   };

@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kBlk) k_init_s1(const double* H1, int64_t n, i
        q += (int64_t)gridDim.x * kBlk) {
     const int64_t r = q / ld, c = q - r * ld;
     double v = 0.0;
-    if (r < n && c < n) v = -H1[r * n + c] / w;
+    if (H1 && r < n && c < n) v = -H1[r * n + c] / w;
     const M mv = (M)v;
     s1[q] = mv;
     if constexpr (SPLIT) {
@@ -226,7 +226,8 @@ hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int6
                           int64_t ld, LayerState* st, int j, double* part, void* s1, void* hi,
                           void* lo, int t, double w_fixed, hipStream_t s) {
   const int use_state = w_fixed > 0.0 ? 0 : 1;
-  hipLaunchKernelGGL(k_maxabs, dim3(kRedBlocks), dim3(kBlk), 0, s, H1, n * n, part);
+  // H1 == NULL: a zero perturbation (the second-order chain without H2)
+  hipLaunchKernelGGL(k_maxabs, dim3(kRedBlocks), dim3(kBlk), 0, s, H1, H1 ? n * n : 0, part);
   hipLaunchKernelGGL(k_s1_setup, dim3(1), dim3(kBlk), 0, s, part, kRedBlocks, st, j, use_state,
                      w_fixed);
   switch (prec) {
@@ -251,11 +252,13 @@ hipError_t launch_init_s1(dmpt_precision prec, const double* H1, int64_t n, int6
 }
 
 // ------------------------------------------------------------------ state reset
-__global__ void k_reset_state(LayerState* st, int k, int max_layers, double nocc, int64_t n) {
+__global__ void k_reset_state(LayerState* st, int k, int order2_slot, int max_layers, double nocc,
+                              int64_t n) {
   // one thread: a few hundred words
   if (threadIdx.x != 0) return;
   st->n_real = (int32_t)n;
   st->k = k;
+  st->order2_slot = order2_slot;
   st->max_layers = max_layers;
   st->nocc = nocc;
   st->n = 0;
@@ -282,9 +285,10 @@ __global__ void k_reset_state(LayerState* st, int k, int max_layers, double nocc
   }
 }
 
-hipError_t launch_reset_state(LayerState* st, int k, int max_layers, double nocc, int64_t n,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(kWave), 0, s, st, k, max_layers, nocc, n);
+hipError_t launch_reset_state(LayerState* st, int k, int order2_slot, int max_layers, double nocc,
+                              int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(kWave), 0, s, st, k, order2_slot, max_layers,
+                     nocc, n);
   return hipGetLastError();
 }
 

@@ -242,7 +242,10 @@ struct Partials {
 
 // Algorithm 2 FroErr^(0) at the D0 layer and, per active response, Algorithm
 // 3 (thread 0 only): FroErr^(1)_n, the parameter-free D1 test (Eq. ConvCrit,
-// C_pt = 9), the next split scale, and the stop flag.  f0sq = ||S - X||_F^2
+// C_pt = 9), the next split scale, and the stop flag.  The second-order chain
+// (slot order2_slot) takes the same test on FroErr^(2)_n = ||S2 - X2||_F from
+// two layers after the D1 layer of the first perturbation: with S0 and S1
+// frozen its map has the same linear part as the first-order map.  f0sq = ||S - X||_F^2
 // (used at the D0 layer), f1sq[j] = ||S1_j - X1_j||_F^2, m1[j] = max|S1_j,n|.
 static __device__ void decide1_apply(LayerState* st, double f0sq, const double* f1sq,
                                      const double* m1, int split, int lo_shift) {
@@ -264,7 +267,11 @@ static __device__ void decide1_apply(LayerState* st, double f0sq, const double* 
       const double f = sqrt(f1sq[j]);
       st->fro1[j][n] = f;
       if (!isfinite(f)) st->error = DMPT_ENONFINITE;
-      if (n - 2 >= st->d0_layer) {
+      // first order: two layers after D0; the second-order chain: two layers
+      // after the D1 layer of the first perturbation (S0 and S1 frozen)
+      const bool armed = j == st->order2_slot ? (st->d1[0] && n - 2 >= st->d1_layer[0])
+                                              : n - 2 >= st->d0_layer;
+      if (armed) {
         const double prev = st->fro1[j][n - 2];
         if (f > 9.0 * st->fro0 * prev || f == 0.0) {
           st->d1[j] = 1;

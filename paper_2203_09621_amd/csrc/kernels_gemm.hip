@@ -15,6 +15,8 @@
 //   acc = (2^t hi_A) hi_B + hi_A lo_B + lo_A hi_B  ( = 2^(t + eA + eB) A B )
 // and the epilogue multiplies by 2^-(t + eA + eB).  The lo*lo term is dropped
 // as in the paper.  The 2^t factor is applied to hi_A in registers (exact).
+// The MFMA's rounding depends on the operand order, so the trace kernel below
+// uses the same order.
 #include <stdlib.h>
 
 #include "layer_common.h"

@@ -91,6 +91,7 @@ def measured_traffic(workload, precision):
 
 
 def oracle_errors(p, P0, P1s):
+    """Relative Frobenius errors of P0 and P1_k, and the oracle's Tr(H1_k P1_k)."""
     from oracle import exact
     t = time.perf_counter()
     if p.basis.kind == "brickwall":
@@ -99,7 +100,8 @@ def oracle_errors(p, P0, P1s):
     else:
         r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
     log(f"oracle reference: {time.perf_counter() - t:.1f} s")
-    return exact.rel_fro(P0, r0), [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)]
+    obs = [float(np.sum(h * r)) for h, r in zip(p.H1, r1s)]   # Tr(H1 P1), H1 symmetric
+    return exact.rel_fro(P0, r0), [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)], obs
 
 
 def cpu_baseline(p, workload, layers):
@@ -311,10 +313,16 @@ def main():
                      "avg_launch_ms": round(prod_ms / max(launches, 1), 4),
                      "launches": launches},
     }
+    # the observable of the response (the polarisability-type contraction)
+    pi = dm.dmpt_contract(H1s, P1s)
+    out["observable"] = {"tr_h1_p1": [float(pi[j, j]) for j in range(len(H1s))]}
     if not args.no_oracle:
-        e0, e1 = oracle_errors(p, P0.cpu().numpy(), [q.cpu().numpy() for q in P1s])
+        e0, e1, obs = oracle_errors(p, P0.cpu().numpy(), [q.cpu().numpy() for q in P1s])
         out["rel_fro_err"] = {"P0": e0, "P1": e1}
-        log(f"errors vs oracle: P0 {e0:.2e}  P1 {[f'{x:.2e}' for x in e1]}")
+        out["observable"]["oracle"] = obs
+        out["observable"]["rel_err"] = [abs(pi[j, j] - o) / abs(o) for j, o in enumerate(obs)]
+        log(f"errors vs oracle: P0 {e0:.2e}  P1 {[f'{x:.2e}' for x in e1]}  "
+            f"Tr(H1 P1) rel {out['observable']['rel_err']}")
     if not args.no_fp64 and args.precision != "fp64":
         dm.dmpt_destroy(ctx)
         ctx = None

@@ -199,6 +199,18 @@ dmpt_status dmpt_batch_info(const dmpt_batch* batch, int32_t* threshold, int32_t
 /* Release a batch.  NULL is allowed. */
 void dmpt_batch_destroy(dmpt_batch* batch);
 
+/* Observables of the response (the polarisability-type contractions of
+ * Sec. V.B): out[a * nb + b] = Tr(A[a] B[b]) for symmetric B[b] (every H1 and
+ * P1 of this library is), evaluated as sum_ij A_ij B_ij in FP64 with a
+ * fixed-order reduction.  A, B: host arrays of na (nb) device pointers
+ * (16-byte aligned) to N x N FP64 matrices; out: host array of na * nb
+ * doubles.  With A = H1_a
+ * and B = P1_b this is Pi_ab = Tr(H1_a P1_b), whose diagonal mean is the
+ * isotropic value.  Errors: EINVAL (NULL or misaligned pointer, na or nb
+ * outside [1, 64]), ENOMEM, EHIP. */
+dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* const* B, int32_t nb,
+                          int64_t N, double* out, void* stream);
+
 /* Short name of a status code (static storage). */
 const char* dmpt_status_str(dmpt_status s);
 

@@ -159,6 +159,24 @@ def invariants2(h0, h1, h2, p0, p1, p2) -> dict:
     }
 
 
+def contraction_matrix(h0: np.ndarray, h1s, nocc: int) -> np.ndarray:
+    """Pi_ab = Tr(H1_a P1_b), the observable behind the polarisability tables
+    of Sec. V.B (isotropic value: the mean of the diagonal).  In the eigenbasis,
+    Pi_ab = 2 sum_{i occ, c virt} (H1_a~)_ci (H1_b~)_ci / (e_i - e_c): symmetric
+    and negative semidefinite."""
+    e, v = eigensystem(h0)
+    check_gap(e, nocc)
+    vo, vv = v[:, :nocc], v[:, nocc:]
+    d = 1.0 / (e[None, :nocc] - e[nocc:, None])
+    t = [vv.T @ (h @ vo) for h in h1s]
+    k = len(h1s)
+    out = np.zeros((k, k))
+    for a in range(k):
+        for b in range(k):
+            out[a, b] = 2.0 * float(np.sum(t[a] * t[b] * d))
+    return out
+
+
 def _apply_layers(m, layers, offsets, block, transpose: bool):
     """In place: M <- Q M (Q = L_last ... L_0) or M <- Q^T M, for block-diagonal
     orthogonal layers L_l = blockdiag(I_offset_l, blocks..., I_rest)."""

@@ -22,7 +22,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
-           "dmpt_response2",
+           "dmpt_response2", "dmpt_contract",
            "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
            "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
@@ -94,6 +94,9 @@ def _load():
     lib.dmpt_response2.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    POINTER(DmptStats)]
     lib.dmpt_response2.restype = c_int32
+    lib.dmpt_contract.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32, c_int64,
+                                  POINTER(c_double), c_void_p]
+    lib.dmpt_contract.restype = c_int32
     lib.dmpt_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
                                  POINTER(c_void_p), POINTER(DmptStats)]
     lib.dmpt_adjoint.restype = c_int32
@@ -221,6 +224,22 @@ def dmpt_response2(ctx: c_void_p, H1, H2=None, P0=None, P1=None, P2=None):
     stats = st.as_dict()
     _check(status, stats)
     return P0, P1, P2, stats
+
+
+def dmpt_contract(As, Bs, stream=None):
+    """dmpt_contract: the matrix Tr(A_a B_b) (B_b symmetric) of device FP64
+    matrices, e.g. Pi_ab = Tr(H1_a P1_b).  Returns a numpy (na, nb) array."""
+    import numpy as np
+    na, nb = len(As), len(Bs)
+    n = As[0].shape[0]
+    for m in list(As) + list(Bs):
+        if tuple(m.shape) != (n, n):
+            raise ValueError("every matrix must be N x N")
+    out = (c_double * (na * nb))()
+    _check(LIB.dmpt_contract((c_void_p * na)(*[_dev(a, "A").value for a in As]), na,
+                             (c_void_p * nb)(*[_dev(b, "B").value for b in Bs]), nb, n, out,
+                             _stream(stream)))
+    return np.array(out[:]).reshape(na, nb)
 
 
 def dmpt_adjoint(ctx: c_void_p, Ws, dH0=None, dH1s=None):

@@ -813,6 +813,36 @@ dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, c
   return done(DMPT_OK, "");
 }
 
+dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* const* B, int32_t nb,
+                          int64_t N, double* out, void* stream) {
+  if (!A || !B || !out || na < 1 || nb < 1 || na > 64 || nb > 64 || N < 1)
+    return fail(DMPT_EINVAL, "bad arguments");
+  for (int i = 0; i < na; ++i)
+    if (!A[i] || (uintptr_t)A[i] % 16) return fail(DMPT_EINVAL, "A[a] NULL or not 16-byte aligned");
+  for (int i = 0; i < nb; ++i)
+    if (!B[i] || (uintptr_t)B[i] % 16) return fail(DMPT_EINVAL, "B[b] NULL or not 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  double *part = nullptr, *dev = nullptr;
+  const int np = na * nb;
+  if (hipMalloc((void**)&part, (size_t)np * kRedBlocks * sizeof(double)) != hipSuccess)
+    return fail(DMPT_ENOMEM, "allocation failed");
+  if (hipMalloc((void**)&dev, (size_t)np * sizeof(double)) != hipSuccess) {
+    hipFree(part);
+    return fail(DMPT_ENOMEM, "allocation failed");
+  }
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < na && e == hipSuccess; ++a)
+    for (int b = 0; b < nb && e == hipSuccess; ++b)
+      e = launch_contract(A[a], B[b], N, part + (size_t)(a * nb + b) * kRedBlocks,
+                          dev + a * nb + b, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dev, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(part);
+  hipFree(dev);
+  return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
+}
+
 dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps, void* stream) {
   if (!H || !eps || N < 1) return fail(DMPT_EINVAL, "bad arguments");
   hipStream_t s = (hipStream_t)stream;

@@ -190,6 +190,9 @@ hipError_t launch_postdecide(LayerState* st, const TileItem* items, int n_items,
 hipError_t launch_copy_out(dmpt_precision prec, const LayerState* st, int which, const void* b0,
                            const void* b1, int64_t ld, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_trace(const double* P, int64_t n, double* out, hipStream_t s);
+// out = Tr(A B) for symmetric B (part: kRedBlocks FP64 partials)
+hipError_t launch_contract(const double* A, const double* B, int64_t n, double* part, double* out,
+                           hipStream_t s);
 hipError_t launch_from_f64(dmpt_precision prec, const double* A, int64_t n, int64_t rows,
                            int64_t ld, int e, int t, void* master, void* hi, void* lo,
                            hipStream_t s);

@@ -379,6 +379,38 @@ hipError_t launch_decide1(LayerState* st, const double* pfro0, const double* pfr
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ observables
+// Tr(A B) for symmetric B as sum_ij A_ij B_ij: FP64 partial per block in a
+// fixed grid; the final sum runs in block order.
+__global__ void __launch_bounds__(kBlk) k_contract(const double* A, const double* B, int64_t total,
+                                                  double* part) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  double v = 0.0;
+  const int64_t pairs = total / 2;
+  for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < pairs;
+       q += (int64_t)gridDim.x * kBlk) {
+    const D2 a = ((const D2*)A)[q], b = ((const D2*)B)[q];
+    v += a[0] * b[0] + a[1] * b[1];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (total & 1)) v += A[total - 1] * B[total - 1];
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void k_contract_final(const double* part, int nb, double* out) {
+  if (threadIdx.x != 0) return;
+  double v = 0.0;
+  for (int i = 0; i < nb; ++i) v += part[i];
+  *out = v;
+}
+
+hipError_t launch_contract(const double* A, const double* B, int64_t n, double* part, double* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_contract, dim3(kRedBlocks), dim3(kBlk), 0, s, A, B, n * n, part);
+  hipLaunchKernelGGL(k_contract_final, dim3(1), dim3(kWave), 0, s, part, kRedBlocks, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ fused split layer
 __global__ void __launch_bounds__(kBlk) k_predecide(LayerState* st, const double* part, int np) {
   predecide_body(st, part, np);

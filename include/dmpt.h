@@ -211,6 +211,28 @@ void dmpt_batch_destroy(dmpt_batch* batch);
 dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* const* B, int32_t nb,
                           int64_t N, double* out, void* stream);
 
+/* ---- non-orthogonal bases (Sec. II.A) ----
+ * Inverse factor of a symmetric positive-definite overlap matrix O (device
+ * FP64 N x N): Z with Z^T O Z = I by the recursion X_n = Z_n^T O Z_n,
+ * Z_{n+1} = Z_n (1.875 I - 1.25 X_n + 0.375 X_n^2) from Z_0 = c I, c^2 = 1 over
+ * the Gershgorin bound of O.  Every iterate is a polynomial in O, so Z is the
+ * symmetric factor O^{-1/2}.  Products run on MFMA in `precision` (DMPT_FP64
+ * or DMPT_FP32).  Stops when ||Z O Z - I||_F < tol (or after max_iter updates);
+ * iters and err (may be NULL) receive the updates done and the last residual.
+ * Writes Z (device FP64 N x N).  Errors: EINVAL, ENOTSUP (other precisions),
+ * ENOMEM, EHIP, ENONFINITE (O not positive definite: divergence), ENOCONV
+ * (tol not reached). */
+dmpt_status dmpt_inverse_factor(int32_t precision, const double* O, int64_t N, double* Z,
+                                int32_t max_iter, double tol, int32_t* iters, double* err,
+                                void* stream);
+
+/* out = Z A Z for symmetric Z and A (device FP64 N x N; out may not alias):
+ * the orthogonalised H_perp = Z^T H Z of a symmetric Z and, back, D = Z D_perp
+ * Z^T.  Products on MFMA in `precision` (DMPT_FP64 or DMPT_FP32).  Errors:
+ * EINVAL, ENOTSUP, ENOMEM, EHIP. */
+dmpt_status dmpt_congruence(int32_t precision, int64_t N, const double* Z, const double* A,
+                            double* out, void* stream);
+
 /* Short name of a status code (static storage). */
 const char* dmpt_status_str(dmpt_status s);
 

@@ -177,6 +177,34 @@ def contraction_matrix(h0: np.ndarray, h1s, nocc: int) -> np.ndarray:
     return out
 
 
+def inverse_factor(o: np.ndarray, tol: float = 1e-14, max_iter: int = 200):
+    """Z with Z^T O Z = I by the recursion of Sec. II.A: X_n = Z_n^T O Z_n,
+    Z_{n+1} = Z_n (1.875 I - 1.25 X_n + 0.375 X_n^2), from Z_0 = I / sqrt(b) with
+    b the Gershgorin bound of O.  Returns (Z, iterations, ||Z^T O Z - I||_F)."""
+    n = o.shape[0]
+    _, b = gershgorin(o)
+    z = np.eye(n) / np.sqrt(b)
+    eye = np.eye(n)
+    for it in range(max_iter + 1):
+        x = z.T @ o @ z
+        r = float(np.linalg.norm(x - eye))
+        if r < tol or it == max_iter:
+            return z, it, r
+        z = z @ (1.875 * eye - 1.25 * x + 0.375 * (x @ x))
+    return z, max_iter, r
+
+
+def generalized_solve(h0: np.ndarray, o: np.ndarray, h1s, nocc: int):
+    """(D0, [D1_k]) in a non-orthogonal basis with overlap O (Sec. II.A:
+    D = Z theta(mu I - Z^T H Z) Z^T): generalised eigenpairs H0 C = O C diag(e)
+    with C^T O C = I (LAPACK sygvd), D0 = C_o C_o^T and D1 = C_v M C_o^T +
+    transpose with M_ai = (C_v^T H1 C_o)_ai / (e_i - e_a)."""
+    import scipy.linalg
+    e, c = scipy.linalg.eigh(h0, o)
+    check_gap(e, nocc)
+    return c[:, :nocc] @ c[:, :nocc].T, [response_from_eigs(e, c, h, nocc) for h in h1s]
+
+
 def _apply_layers(m, layers, offsets, block, transpose: bool):
     """In place: M <- Q M (Q = L_last ... L_0) or M <- Q^T M, for block-diagonal
     orthogonal layers L_l = blockdiag(I_offset_l, blocks..., I_rest)."""

@@ -22,7 +22,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
-           "dmpt_response2", "dmpt_contract",
+           "dmpt_response2", "dmpt_contract", "dmpt_inverse_factor", "dmpt_congruence",
            "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
            "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
@@ -97,6 +97,11 @@ def _load():
     lib.dmpt_contract.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32, c_int64,
                                   POINTER(c_double), c_void_p]
     lib.dmpt_contract.restype = c_int32
+    lib.dmpt_inverse_factor.argtypes = [c_int32, c_void_p, c_int64, c_void_p, c_int32, c_double,
+                                        POINTER(c_int32), POINTER(c_double), c_void_p]
+    lib.dmpt_inverse_factor.restype = c_int32
+    lib.dmpt_congruence.argtypes = [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.dmpt_congruence.restype = c_int32
     lib.dmpt_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
                                  POINTER(c_void_p), POINTER(DmptStats)]
     lib.dmpt_adjoint.restype = c_int32
@@ -240,6 +245,41 @@ def dmpt_contract(As, Bs, stream=None):
                              (c_void_p * nb)(*[_dev(b, "B").value for b in Bs]), nb, n, out,
                              _stream(stream)))
     return np.array(out[:]).reshape(na, nb)
+
+
+def dmpt_inverse_factor(O, precision: str = "fp64", max_iter: int = 60, tol: float = 1e-12,
+                        Z=None, stream=None):
+    """dmpt_inverse_factor: Z = O^{-1/2} (Z O Z = I).  Returns (Z, iters, err)."""
+    torch = _torch()
+    Z = torch.empty_like(O) if Z is None else Z
+    it, err = c_int32(0), c_double(0.0)
+    _check(LIB.dmpt_inverse_factor(PRECISION[precision], _dev(O, "O"), O.shape[0], _dev(Z, "Z"),
+                                   max_iter, tol, byref(it), byref(err), _stream(stream)),
+           {"iters": it.value, "err": err.value})
+    return Z, it.value, err.value
+
+
+def dmpt_congruence(Z, A, precision: str = "fp64", out=None, stream=None):
+    """dmpt_congruence: Z A Z for symmetric Z and A (device FP64)."""
+    torch = _torch()
+    out = torch.empty_like(A) if out is None else out
+    _check(LIB.dmpt_congruence(PRECISION[precision], A.shape[0], _dev(Z, "Z"), _dev(A, "A"),
+                               _dev(out, "out"), _stream(stream)))
+    return out
+
+
+def solve_nonorth(H0, O, H1s, nocc: int, precision: str = "split_fp16",
+                  ortho_precision: str = "fp64", **kw):
+    """P0 and P1_k in a non-orthogonal basis with overlap O (all device FP64):
+    Z = O^{-1/2}, H_perp = Z H Z, the response in the orthogonal basis, then
+    P = Z P_perp Z (Sec. II.A).  Every step is a library call."""
+    Z, _, _ = dmpt_inverse_factor(O, precision=ortho_precision)
+    Hp = dmpt_congruence(Z, H0, precision=ortho_precision)
+    H1p = [dmpt_congruence(Z, h, precision=ortho_precision) for h in H1s]
+    P0p, P1ps, st = solve(Hp, H1p, nocc, precision=precision, **kw)
+    P0 = dmpt_congruence(Z, P0p, precision=ortho_precision)
+    P1s = [dmpt_congruence(Z, q, precision=ortho_precision) for q in P1ps]
+    return P0, P1s, st
 
 
 def dmpt_adjoint(ctx: c_void_p, Ws, dH0=None, dH1s=None):

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdmpt.so")
 SOURCES = ["kernels_gemm.hip", "kernels_layer.hip", "kernels_adjoint.hip", "dmpt_api.hip",
-           "dmpt_batch.hip"]
+           "dmpt_batch.hip", "dmpt_ortho.hip"]
 ARCH = "gfx950"
 
 

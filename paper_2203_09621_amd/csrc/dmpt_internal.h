@@ -130,7 +130,9 @@ struct ProductArgs {
   double* part_f;            // fused: per-item FP64 sums (squares), slot slot_base + item
   double* part_m;            // fused: per-item max |S1_new|
   int32_t slot_base;
-  int32_t pad0;
+  int32_t mode;              // direct forms: 0 layer products; 1 one product C = A B (A = s_hi,
+                             // B = s1_hi[0], C = x) on upper tiles, mirrored (symmetric C);
+                             // 2 the same on all tiles, no mirror (general C)
   const TileItem* items;
   const LayerState* state;   // NULL: compute every item, scales taken from s1_exp
   int32_t s1_exp[kMaxK];     // used when state == NULL
@@ -144,6 +146,9 @@ struct ProductArgs {
 // layer products (kernels_gemm.hip)
 int product_tile(dmpt_precision prec);   // output tile edge used by the product kernels
 hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s);
+// Tile items of an Np x Np output for the single-product modes: upper tiles
+// (mode 1) or all tiles (mode 2), tile edge product_tile(prec).
+void product_items(int T, int mode, TileItem* out);   // T (T + 1) / 2 or T * T entries
 // Fused split layer with 256- or 128-row tiles (a.probs set): the products of
 // layer n and, in their epilogue, the layer update, the next split and the
 // per-item partial sums; sigma and the update flags come from each problem's

@@ -516,8 +516,8 @@ k_products_direct(const ProductArgs a) {
   const int64_t ld = a.ld;
   const int j = it.out - 1;
   // the second-order chain: X2 = S1_0 S1_0 + S S2 + S2 S (S2 = s1_hi[j])
-  const bool second = it.out > 0 && a.state && j == a.state->order2_slot;
-  const int nprod = it.out == 0 ? 1 : (second ? 3 : 2);
+  const bool second = a.mode == 0 && it.out > 0 && a.state && j == a.state->order2_slot;
+  const int nprod = (a.mode != 0 || it.out == 0) ? 1 : (second ? 3 : 2);
   // out 0: S S;  out 1 + j: A B + B A with A = a_op[j] (default S), B = s1_hi[j];
   // X2: S1_0 S1_0, S S2, S2 S.  Operands of product p: [A rows, B rows].
   const T *Q0[2], *Q1[2], *Q2[2];
@@ -525,7 +525,10 @@ k_products_direct(const ProductArgs a) {
     const T* s = (const T*)a.s_hi;
     const T* aa = s;
     const T* bb = s;
-    if (it.out != 0) {
+    if (a.mode != 0) {
+      aa = s;                                  // one product A B, A = s_hi, B = s1_hi[0]
+      bb = (const T*)a.s1_hi[0];
+    } else if (it.out != 0) {
       aa = a.a_op[j] ? (const T*)a.a_op[j] : s;
       bb = (const T*)a.s1_hi[j];
     }
@@ -617,8 +620,9 @@ k_products_direct(const ProductArgs a) {
     __syncthreads();
   }
 
-  T* C = (T*)(it.out == 0 ? a.x : a.x1[j]);
+  T* C = (T*)((a.mode != 0 || it.out == 0) ? a.x : a.x1[j]);
   const bool diag = it.ti == it.tj;
+  const bool mirror = a.mode != 2;
 #pragma unroll
   for (int m = 0; m < FM; ++m)
 #pragma unroll
@@ -629,8 +633,12 @@ k_products_direct(const ProductArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int64_t gr = gr0 + D::row(lane, r);
         const T v = acc[m][n][r];
-        if (!diag || gr <= gc) C[gr * ld + gc] = v;
-        if (!diag || gr < gc) C[gc * ld + gr] = v;
+        if (!mirror) {
+          C[gr * ld + gc] = v;
+        } else {
+          if (!diag || gr <= gc) C[gr * ld + gc] = v;
+          if (!diag || gr < gc) C[gc * ld + gr] = v;
+        }
       }
     }
   }  // items
@@ -644,6 +652,19 @@ constexpr int kDirBK32 = 32, kDirBK64 = 16;
 
 int product_tile(dmpt_precision prec) {
   return (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16) ? kSplitBM : kDirBM;
+}
+
+void product_items(int T, int mode, TileItem* out) {
+  int k = 0;
+  for (int ti = 0; ti < T; ++ti)
+    for (int tj = mode == 2 ? 0 : ti; tj < T; ++tj) {
+      TileItem it;
+      it.out = 0;
+      it.prob = 0;
+      it.ti = ti;
+      it.tj = tj;
+      out[k++] = it;
+    }
 }
 
 static int device_cus() {
@@ -709,6 +730,8 @@ hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_
   // tiles cover [0, kdim)^2 exactly; rows must keep 16-byte alignment
   if (a.kdim % product_tile(prec) != 0 || a.ld < a.kdim || a.ld % 8 != 0)
     return hipErrorInvalidValue;
+  if (a.mode != 0 && (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16 || a.state))
+    return hipErrorInvalidValue;               // single products: direct forms, no state
   switch (prec) {
     case DMPT_SPLIT_FP16:
       return launch_split<_Float16, false>(a, s);

@@ -14,6 +14,7 @@ from .synthetic import (  # noqa: F401
     diag_coordinates,
     dense_gapped_problem,
     banded_gapped_problem,
+    nonorth_problem,
     config1,
     config2,
     config3,

@@ -73,6 +73,7 @@ class Problem:
     basis: Basis
     seed: int
     W: Optional[np.ndarray] = None
+    O: Optional[np.ndarray] = None     # overlap of a non-orthogonal basis (None: orthonormal)
 
     @property
     def k(self) -> int:
@@ -147,6 +148,24 @@ def dense_gapped_problem(n: int, nocc: int, gap: float, seed: int, *, name: str 
     w = sym_normal(rng, n, 1.0) if with_w else None
     return Problem(name or f"dense_N{n}", n, nocc, h0, h1s, gap,
                    Basis(e=e, kind="dense", Q=q), seed, w)
+
+
+def nonorth_problem(n: int, nocc: int, gap: float, seed: int, *, name: str = "", k: int = 1,
+                    h1_std: float = 0.01, spread: float = 2.0, width: float = 10.0) -> Problem:
+    """A non-orthogonal basis: B = Q_b diag(s) with Haar Q_b and s log-uniform in
+    [1/sqrt(spread), sqrt(spread)], overlap O = B B^T (condition number up to
+    spread^2), H0 = B H_perp B^T and H1 = B H1_perp B^T with (H_perp, H1_perp) the
+    dense gapped recipe.  The generalised problem H0 c = e O c then has exactly
+    the gapped spectrum of H_perp."""
+    p = dense_gapped_problem(n, nocc, gap, seed, h1="dense", k=k, h1_std=h1_std, width=width)
+    rng = np.random.default_rng(seed + 7919)
+    qb = haar_orthogonal(rng, n)
+    sc = np.exp(rng.uniform(-0.5, 0.5, n) * np.log(spread))
+    b = qb * sc[None, :]
+    o = _symmetrize(b @ b.T)
+    h0 = _symmetrize(b @ p.H0 @ b.T)
+    h1s = [_symmetrize(b @ h @ b.T) for h in p.H1]
+    return Problem(name or f"nonorth_N{n}", n, nocc, h0, h1s, gap, p.basis, seed, None, o)
 
 
 def banded_gapped_problem(n: int, nocc: int, gap: float, seed: int, *, block: int = 128,

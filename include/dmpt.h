@@ -136,6 +136,26 @@ dmpt_status dmpt_response(dmpt_ctx* ctx, const double* const* H1, int32_t k, dou
 dmpt_status dmpt_response2(dmpt_ctx* ctx, const double* H1, const double* H2, double* P0,
                            double* P1, double* P2, dmpt_stats* st);
 
+/* Induced field of a self-consistent (coupled-perturbed) response: given the
+ * current first-order density matrix P1 (device FP64 N x N), write G = H1_ind[P1]
+ * (device FP64 N x N, symmetric) with work enqueued on `stream`, or finish it
+ * before returning.  The physics builder stays with the caller. */
+typedef void (*dmpt_field_fn)(void* user, const double* P1, double* G, void* stream);
+
+/* Self-consistent first-order response (the coupled-perturbed loop of
+ * Sec. V.B): P1 = DP[H1 + G[P1]] by the fixed-point iteration
+ *   H_eff <- (1 - mix) H_eff + mix (H1 + field(P1)),   P1 <- response(H_eff),
+ * from H_eff = H1, each response by Algorithms 1-3 in the context's precision.
+ * Stops when ||P1_new - P1_old||_F / ||P1_new||_F < tol.  G is caller-provided
+ * workspace (device FP64 N x N) that `field` fills; P0 may be NULL; iters and
+ * change (may be NULL) receive the field evaluations and the last relative
+ * change.  Allocates two N x N FP64 buffers for the duration of the call.
+ * Errors: as dmpt_response, ENOCONV when max_iter field evaluations do not
+ * reach tol, ENONFINITE on divergence.  The adjoint does not cover it. */
+dmpt_status dmpt_cpscf(dmpt_ctx* ctx, const double* H1, dmpt_field_fn field, void* user,
+                       double mix, double tol, int32_t max_iter, double* P0, double* P1,
+                       double* G, int32_t* iters, double* change, dmpt_stats* st);
+
 /* Reverse mode of the layer recursion for L = sum_j Tr(P1_j W_j), applied to
  * the most recent successful dmpt_response of this context (same k, k <= 3;
  * the context needs ckpt_every > 0).  W[j] (host array of device FP64 N x N)

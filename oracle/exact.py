@@ -177,6 +177,20 @@ def contraction_matrix(h0: np.ndarray, h1s, nocc: int) -> np.ndarray:
     return out
 
 
+def cpscf_linear(h0: np.ndarray, h1: np.ndarray, nocc: int, c: float) -> np.ndarray:
+    """Self-consistent first-order response for the induced field G[P1] = c P1:
+    P1 = DP[H1 + c P1] (the coupled-perturbed fixed point of Sec. V.B with a
+    linear response kernel).  In the eigenbasis the fixed point is
+    P1~_ai = H1~_ai / (e_i - e_a - c) on the virtual-occupied block."""
+    e, v = eigensystem(h0)
+    check_gap(e, nocc)
+    vo, vv = v[:, :nocc], v[:, nocc:]
+    y = vv.T @ (h1 @ vo)
+    cm = y / (e[None, :nocc] - e[nocc:, None] - c)
+    m = vv @ (cm @ vo.T)
+    return m + m.T
+
+
 def inverse_factor(o: np.ndarray, tol: float = 1e-14, max_iter: int = 200):
     """Z with Z^T O Z = I by the recursion of Sec. II.A: X_n = Z_n^T O Z_n,
     Z_{n+1} = Z_n (1.875 I - 1.25 X_n + 0.375 X_n^2), from Z_0 = I / sqrt(b) with

@@ -23,6 +23,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
            "dmpt_response2", "dmpt_contract", "dmpt_inverse_factor", "dmpt_congruence",
+           "dmpt_cpscf",
            "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
            "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
@@ -69,6 +70,10 @@ class DmptProblemStats(ctypes.Structure):
                 "idem0": self.idem0, "idem1": list(self.idem1[:k])}
 
 
+# induced-field callback of dmpt_cpscf: (user, P1, G, stream)
+_FIELD_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p, c_void_p)
+
+
 class DmptError(RuntimeError):
     def __init__(self, status: int, message: str, stats: dict | None = None):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
@@ -97,6 +102,10 @@ def _load():
     lib.dmpt_contract.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32, c_int64,
                                   POINTER(c_double), c_void_p]
     lib.dmpt_contract.restype = c_int32
+    lib.dmpt_cpscf.argtypes = [c_void_p, c_void_p, _FIELD_FN, c_void_p, c_double, c_double,
+                               c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_int32),
+                               POINTER(c_double), POINTER(DmptStats)]
+    lib.dmpt_cpscf.restype = c_int32
     lib.dmpt_inverse_factor.argtypes = [c_int32, c_void_p, c_int64, c_void_p, c_int32, c_double,
                                         POINTER(c_int32), POINTER(c_double), c_void_p]
     lib.dmpt_inverse_factor.restype = c_int32
@@ -245,6 +254,38 @@ def dmpt_contract(As, Bs, stream=None):
                              (c_void_p * nb)(*[_dev(b, "B").value for b in Bs]), nb, n, out,
                              _stream(stream)))
     return np.array(out[:]).reshape(na, nb)
+
+
+def dmpt_cpscf(ctx: c_void_p, H1, field, mix: float = 1.0, tol: float = 1e-8,
+               max_iter: int = 50, P0=None, P1=None, G=None):
+    """dmpt_cpscf: self-consistent first-order response P1 = DP[H1 + field(P1)].
+    ``field(P1, G)`` writes the induced field into the tensor G (torch ops).
+    Returns (P0, P1, iters, change, stats)."""
+    torch = _torch()
+    P0 = torch.empty_like(H1) if P0 is None else P0
+    P1 = torch.empty_like(H1) if P1 is None else P1
+    G = torch.empty_like(H1) if G is None else G
+    errors = []
+
+    def cb(user, p1, g, stream):
+        try:
+            torch.cuda.synchronize()        # P1 of the library's stream is complete
+            field(P1, G)
+            torch.cuda.synchronize()        # G is complete before the library reads it
+        except Exception as exc:            # noqa: BLE001 - reported after the call
+            errors.append(exc)
+            G.fill_(float("nan"))           # the next response then stops with ENONFINITE
+            torch.cuda.synchronize()
+
+    fn = _FIELD_FN(cb)
+    it, ch = c_int32(0), c_double(0.0)
+    st = DmptStats()
+    status = LIB.dmpt_cpscf(ctx, _dev(H1, "H1"), fn, None, mix, tol, max_iter, _dev(P0, "P0"),
+                            _dev(P1, "P1"), _dev(G, "G"), byref(it), byref(ch), byref(st))
+    if errors:
+        raise errors[0]
+    _check(status, {"iters": it.value, "change": ch.value})
+    return P0, P1, it.value, ch.value, st.as_dict()
 
 
 def dmpt_inverse_factor(O, precision: str = "fp64", max_iter: int = 60, tol: float = 1e-12,

@@ -4,6 +4,7 @@
 // by single-workgroup kernels on the device and stored in a LayerState, which
 // the layer kernels read.  The host looks at the device stop flag every
 // `poll_every` layers; kernels of layers enqueued after the stop return at once.
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -577,6 +578,69 @@ dmpt_status dmpt_response(dmpt_ctx* c, const double* const* H1, int32_t k, doubl
   for (int j = 0; j < k; ++j)
     if (!H1[j] || !P1[j]) return fail(DMPT_EINVAL, "NULL H1[j] or P1[j]");
   return run_response(c, H1, k, false, nullptr, P0, P1, nullptr, stats);
+}
+
+dmpt_status dmpt_cpscf(dmpt_ctx* c, const double* H1, dmpt_field_fn field, void* user,
+                       double mix, double tol, int32_t max_iter, double* P0, double* P1,
+                       double* G, int32_t* iters, double* change, dmpt_stats* stats) {
+  if (!c) return fail(DMPT_EINVAL, "ctx is NULL");
+  if (!H1 || !field || !P1 || !G) return fail(DMPT_EINVAL, "NULL H1, field, P1 or G");
+  if (!(mix > 0.0 && mix <= 1.0) || !(tol > 0.0) || max_iter < 1)
+    return fail(DMPT_EINVAL, "need 0 < mix <= 1, tol > 0, max_iter >= 1");
+  hipStream_t s = c->stream;
+  const int64_t n = c->n;
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  double *heff = nullptr, *prev = nullptr, *part = nullptr, *dn = nullptr;
+  auto release = [&]() {
+    hipStreamSynchronize(s);
+    if (heff) hipFree(heff);
+    if (prev) hipFree(prev);
+    if (part) hipFree(part);
+    if (dn) hipFree(dn);
+  };
+  if (hipMalloc((void**)&heff, bytes) != hipSuccess || hipMalloc((void**)&prev, bytes) != hipSuccess ||
+      hipMalloc((void**)&part, 2 * kRedBlocks * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&dn, 2 * sizeof(double)) != hipSuccess) {
+    release();
+    return fail(DMPT_ENOMEM, "allocation failed");
+  }
+  dmpt_status r = DMPT_OK;
+  double ch = INFINITY;
+  int it = 0;
+  hipError_t e = hipMemcpyAsync(heff, H1, bytes, hipMemcpyDeviceToDevice, s);
+  const double* hp[1] = {heff};
+  double* pp[1] = {P1};
+  if (e == hipSuccess) r = run_response(c, hp, 1, false, nullptr, P0, pp, nullptr, stats);
+  while (e == hipSuccess && r == DMPT_OK && it < max_iter) {
+    // induced field of the current response, then the mixed effective perturbation
+    e = hipMemcpyAsync(prev, P1, bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) break;
+    field(user, P1, G, (void*)s);
+    ++it;
+    e = launch_mix(H1, G, heff, mix, n, s);
+    if (e != hipSuccess) break;
+    r = run_response(c, hp, 1, false, nullptr, P0, pp, nullptr, stats);
+    if (r != DMPT_OK) break;
+    double h[2] = {0.0, 0.0};
+    e = launch_diff_norms(P1, prev, n, part, dn, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, dn, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) break;
+    ch = h[1] > 0.0 ? sqrt(h[0] / h[1]) : sqrt(h[0]);
+    if (!isfinite(ch)) {
+      r = fail(DMPT_ENONFINITE, "self-consistent response diverged");
+      break;
+    }
+    if (ch < tol) break;
+  }
+  release();
+  if (iters) *iters = it;
+  if (change) *change = ch;
+  c->last_k = 0;                       // the adjoint does not cover the self-consistent loop
+  if (e != hipSuccess) return fail(DMPT_EHIP, hipGetErrorString(e));
+  if (r != DMPT_OK) return r;
+  if (!(ch < tol)) return fail(DMPT_ENOCONV, "self-consistent response: tolerance not reached");
+  return DMPT_OK;
 }
 
 dmpt_status dmpt_response2(dmpt_ctx* c, const double* H1, const double* H2, double* P0,

@@ -195,6 +195,12 @@ hipError_t launch_postdecide(LayerState* st, const TileItem* items, int n_items,
 hipError_t launch_copy_out(dmpt_precision prec, const LayerState* st, int which, const void* b0,
                            const void* b1, int64_t ld, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_trace(const double* P, int64_t n, double* out, hipStream_t s);
+// self-consistent response: heff = (1 - mix) heff + mix (h1 + g); out[0] = ||a - b||^2,
+// out[1] = ||a||^2 (part: 2 kRedBlocks FP64 partials)
+hipError_t launch_mix(const double* h1, const double* g, double* heff, double mix, int64_t n,
+                      hipStream_t s);
+hipError_t launch_diff_norms(const double* a, const double* b, int64_t n, double* part,
+                             double* out, hipStream_t s);
 // out = Tr(A B) for symmetric B (part: kRedBlocks FP64 partials)
 hipError_t launch_contract(const double* A, const double* B, int64_t n, double* part, double* out,
                            hipStream_t s);

@@ -411,6 +411,57 @@ hipError_t launch_contract(const double* A, const double* B, int64_t n, double* 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ self-consistent response
+// heff = (1 - mix) heff + mix (h1 + g)
+__global__ void __launch_bounds__(kBlk) k_mix(const double* h1, const double* g, double* heff,
+                                             double mix, int64_t total) {
+  for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * kBlk)
+    heff[q] = (1.0 - mix) * heff[q] + mix * (h1[q] + g[q]);
+}
+
+hipError_t launch_mix(const double* h1, const double* g, double* heff, double mix, int64_t n,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_mix, dim3(2048), dim3(kBlk), 0, s, h1, g, heff, mix, n * n);
+  return hipGetLastError();
+}
+
+// partials of ||a - b||^2 (part[0..nb)) and ||a||^2 (part[nb..2 nb)); out[0..1] their sums
+__global__ void __launch_bounds__(kBlk) k_diff_norms(const double* a, const double* b,
+                                                    int64_t total, double* part) {
+  double d2 = 0.0, a2 = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * kBlk) {
+    const double d = a[q] - b[q];
+    d2 += d * d;
+    a2 += a[q] * a[q];
+  }
+  d2 = block_sum(d2);
+  a2 = block_sum(a2);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = d2;
+    part[gridDim.x + blockIdx.x] = a2;
+  }
+}
+
+__global__ void k_diff_norms_final(const double* part, int nb, double* out) {
+  if (threadIdx.x != 0) return;
+  double d2 = 0.0, a2 = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    d2 += part[i];
+    a2 += part[nb + i];
+  }
+  out[0] = d2;
+  out[1] = a2;
+}
+
+hipError_t launch_diff_norms(const double* a, const double* b, int64_t n, double* part,
+                             double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diff_norms, dim3(kRedBlocks), dim3(kBlk), 0, s, a, b, n * n, part);
+  hipLaunchKernelGGL(k_diff_norms_final, dim3(1), dim3(kWave), 0, s, part, kRedBlocks, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ fused split layer
 __global__ void __launch_bounds__(kBlk) k_predecide(LayerState* st, const double* part, int np) {
   predecide_body(st, part, np);

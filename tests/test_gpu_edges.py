@@ -1,0 +1,106 @@
+"""Edge cases and full-size parity of the HIP path against the FP64 oracle:
+the smallest problem (N = 2, the 2x2 closed form), extreme occupations, a zero
+perturbation, the maximum number of responses, and configurations 2 and 3 at
+their full sizes (N = 4096 with three coordinate perturbations; N = 16384
+banded against the exact factored oracle)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SPLIT_TOL = 1e-3
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_2203_09621_amd as dm
+    return dm
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _solve(dm, h0, h1s, nocc, precision, **kw):
+    P0, P1s, st = dm.solve(_cuda(h0), [_cuda(h) for h in h1s], nocc, precision=precision, **kw)
+    return P0.cpu().numpy(), [q.cpu().numpy() for q in P1s], st
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("split_fp16", SPLIT_TOL),
+                                           ("split_bf16", SPLIT_TOL)])
+def test_two_by_two(dm, precision, tol):
+    """H = [[-1, l b], [l b, 1]]: P0 = diag(1, 0), P1 = -(b/2) offdiag."""
+    b = 0.3
+    h0 = np.diag([-1.0, 1.0])
+    h1 = np.array([[0.0, b], [b, 0.0]])
+    P0, (P1,), st = _solve(dm, h0, [h1], 1, precision)
+    assert st["converged"]
+    assert np.abs(P0 - np.diag([1.0, 0.0])).max() < tol
+    assert np.abs(P1 - np.array([[0.0, -b / 2], [-b / 2, 0.0]])).max() < tol * b
+
+
+@pytest.mark.parametrize("nocc", [1, 199])
+def test_extreme_occupations(dm, nocc):
+    from oracle import exact
+    from workloads import dense_gapped_problem
+    p = dense_gapped_problem(200, nocc, 1.0, 1401 + nocc, h1="dense", k=1)
+    P0, (P1,), st = _solve(dm, p.H0, p.H1, nocc, "split_fp16")
+    r0, (r1,) = exact.solve(p.H0, p.H1, nocc)
+    e0, e1 = exact.rel_fro(P0, r0), exact.rel_fro(P1, r1)
+    print(f"Nocc={nocc}: layers {st['layers']} errors {e0:.2e} {e1:.2e}", flush=True)
+    assert st["converged"] and e0 < SPLIT_TOL and e1 < SPLIT_TOL
+    assert abs(st["trace_p0"] - nocc) < 1e-3 * nocc
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_fp16"])
+def test_zero_perturbation(dm, precision):
+    """H1 = 0: P1 = 0 exactly, and the D1 test fires on FroErr = 0 (reading 5)."""
+    from workloads import config1
+    c1 = config1()
+    P0, (P1,), st = _solve(dm, c1.H0, [np.zeros_like(c1.H0)], c1.nocc, precision)
+    assert st["converged"]
+    assert np.abs(P1).max() == 0.0
+    assert st["d1_layer"][0] == st["d0_layer"] + 2
+
+
+def test_maximum_number_of_responses(dm):
+    from oracle import exact
+    from workloads import dense_gapped_problem
+    p = dense_gapped_problem(384, 192, 0.8, 1411, h1="dense", k=8)
+    P0, P1s, st = _solve(dm, p.H0, p.H1, p.nocc, "split_fp16")
+    r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+    errs = [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)]
+    print(f"k=8: layers {st['layers']} d1 {st['d1_layer']} worst P1 error {max(errs):.2e}",
+          flush=True)
+    assert st["converged"] and len(P1s) == 8 and max(errs) < SPLIT_TOL
+
+
+def test_full_size_configuration2(dm):
+    """N = 4096, Nocc = 2048, gap 0.5, three coordinate perturbations."""
+    from oracle import exact
+    from workloads import config2
+    p = config2()
+    r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+    for precision in ("split_fp16", "split_bf16"):
+        P0, P1s, st = _solve(dm, p.H0, p.H1, p.nocc, precision)
+        e = [exact.rel_fro(P0, r0)] + [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)]
+        print(f"configuration 2 {precision}: layers {st['layers']} errors {e}", flush=True)
+        assert st["converged"] and max(e) < SPLIT_TOL
+
+
+def test_full_size_configuration3(dm):
+    """N = 16384 banded, gap 0.2, split FP16, against the exact factored oracle."""
+    from oracle import exact
+    from workloads import config3
+    p = config3()
+    P0, (P1,), st = _solve(dm, p.H0, p.H1, p.nocc, "split_fp16")
+    r0, (r1,) = exact.solve_from_brickwall(p.basis.e, p.basis.layers, p.basis.layer_offsets(),
+                                           p.basis.block, p.H1, p.nocc)
+    e0, e1 = exact.rel_fro(P0, r0), exact.rel_fro(P1, r1)
+    print(f"configuration 3: layers {st['layers']} errors P0 {e0:.2e} P1 {e1:.2e}", flush=True)
+    assert st["converged"] and e0 < SPLIT_TOL and e1 < SPLIT_TOL
+    assert abs(st["trace_p0"] - p.nocc) < 1e-2

@@ -34,6 +34,18 @@ __device__ __forceinline__ int xcd_remap(int b, int g) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Workgroup-uniform values read from memory the kernel also writes come back
+// in vector registers; these put them in scalar registers for address
+// arithmetic.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) { return (T*)uni((int64_t)p); }
+
 // ------------------------------------------------------------------ split form
 template <typename T16> struct Split16;
 
@@ -86,6 +98,12 @@ struct VmWait {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   static constexpr int imm = (N & 15) | (((N >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
 };
+// ... and until at most N LDS operations are outstanding, the others free.
+template <int N>
+struct LgkWait {
+  static_assert(N >= 0 && N < 16, "lgkmcnt range");
+  static constexpr int imm = 15 | (3 << 14) | (7 << 4) | (N << 8);
+};
 
 // Plain launches store X and X1_j.  Fused launches (FUSED) apply the layer
 // update in the epilogue instead: with sigma of the problem's state,
@@ -115,7 +133,7 @@ k_products_split(const ProductArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
+  const int wave = uni(tid / kWave);
   const int wm = wave / WGN, wn = wave % WGN;
   // Loads go straight from global memory into LDS (global_load_lds_dwordx4):
   // lane l of a wave writes the 16-byte slot l of the wave's 1 KB destination,
@@ -179,8 +197,14 @@ k_products_split(const ProductArgs a) {
     }
   }
   const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BN;
-  const int kt_per = (int)(kdim / BK);
-  const int ktiles = nprod * kt_per;
+  const int kt_per = uni((int)(kdim / BK));
+  const int ktiles = uni(nprod * kt_per);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    Q0[r] = uni(Q0[r]);
+    Q1[r] = uni(Q1[r]);
+    Q2[r] = uni(Q2[r]);
+  }
 
   // Operands are panel-major: the k-tile kt of row tile I is the contiguous
   // block (I * kblocks + kt) of kPanelRows x kPanelK elements.  Per-thread
@@ -188,23 +212,39 @@ k_products_split(const ProductArgs a) {
   // i, so every load round adds only a wave-uniform offset.
   static_assert(kPanelRows % BM == 0 && BK == kPanelK, "tile inside a panel block");
   static_assert((RPL >> SWZ) % CH == 0, "swizzle must repeat every load round");
-  const int64_t kblocks = pdim / kPanelK;
+  static_assert(STAGES == 2 && BK == 32, "two stages of two 16-wide k steps");
+  const int64_t kblocks = uni(pdim / kPanelK);
   const int csrc = lsl ^ ((lrow >> SWZ) & (CH - 1));
   const int voff = lrow * kPanelK + csrc * 8;
-  auto issue = [&](int t) {
-    const int p = t / kt_per;
-    const int64_t kt = t - p * kt_per;
-    u32x4* dst_stage = lds + (t % STAGES) * STAGE;
+  const int64_t offa = uni((row_a0 / kPanelRows) * kblocks * (kPanelRows * kPanelK) +
+                           (row_a0 % kPanelRows) * kPanelK);
+  const int64_t offb = uni((row_b0 / kPanelRows) * kblocks * (kPanelRows * kPanelK) +
+                           (row_b0 % kPanelRows) * kPanelK);
+  // Tile t of the concatenated k range goes to stage t % 2.  Past the end the
+  // last tile is fetched again (into a stage nobody reads any more), so the
+  // loop body has no branches.  One load round moves RPL rows of one array.
+  struct Fetch { const uint16_t* q[4]; u32x4* dst; };
+  auto prep = [&](int t0) {
+    Fetch f;
+    const int t = t0 < ktiles ? t0 : ktiles - 1;
+    const int p = (t >= kt_per) + (t >= 2 * kt_per);
+    const int64_t kofs = (int64_t)(t - p * kt_per) * (kPanelRows * kPanelK);
 #pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
-      const int arr = (i * RPL) / BM;             // compile-time after unrolling
-      const int64_t row0 = arr < 2 ? row_a0 : row_b0;
-      const int64_t soff = ((row0 / kPanelRows) * kblocks + kt) * (kPanelRows * kPanelK) +
-                           (row0 % kPanelRows + (int64_t)(i * RPL - arr * BM)) * kPanelK;
-      const uint16_t* basep = (p == 0 ? Q0[arr] : (p == 1 ? Q1[arr] : Q2[arr])) + soff;
-      u32x4* dst = dst_stage + (i * RPL + wave * RPW) * CH;            // wave-uniform
-      __builtin_amdgcn_global_load_lds((const void*)(basep + voff), (void*)dst, 16, 0, 0);
-    }
+    for (int r = 0; r < 4; ++r)
+      f.q[r] = (p == 0 ? Q0[r] : (p == 1 ? Q1[r] : Q2[r])) + (r < 2 ? offa : offb) + kofs;
+    f.dst = lds + (t0 & 1) * STAGE;
+    return f;
+  };
+  auto issue_round = [&](const Fetch& f, int i) {
+    const int arr = (i * RPL) / BM;               // compile-time after unrolling
+    const uint16_t* basep = f.q[arr] + (i * RPL - arr * BM) * kPanelK;
+    u32x4* dst = f.dst + (i * RPL + wave * RPW) * CH;                  // wave-uniform
+    __builtin_amdgcn_global_load_lds((const void*)(basep + voff), (void*)dst, 16, 0, 0);
+  };
+  auto issue = [&](int t0) {
+    const Fetch f = prep(t0);
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) issue_round(f, i);
   };
 
   f32x16 acc[FM][FN];
@@ -215,69 +255,101 @@ k_products_split(const ProductArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.0f;
 
-  // Prologue: tiles 0 .. STAGES-2 in flight, wait for tile 0 (and for the
-  // previous item's stores, which share the counter).
+  // Fragments of one 16-wide k step: rows of A (hi, lo) and of B (hi, lo).
+  // Fragment g: hi_A m = g, lo_A m = g - FM, hi_B n = g - 2 FM, lo_B n = g - 2 FM - FN.
+  constexpr int NF = 2 * (FM + FN);              // LDS reads per k step
+  constexpr int NM = 3 * FM * FN;                // MFMAs per k step
+  struct Frag { V ah[FM], al[FM], bh[FN], bl[FN]; };
+  auto read_one = [&](int stage, int kk, Frag& f, int g) {
+    const u32x4* base = lds + stage * STAGE;
+    const int c = kk * 2 + (lane >> 5);
+    const bool a_side = g < 2 * FM;
+    const int idx = a_side ? g % FM : (g - 2 * FM) % FN;
+    const bool lo = a_side ? g >= FM : g >= 2 * FM + FN;
+    const int R = (a_side ? wm * WTM + idx * 32 : 2 * BM + wn * WTN + idx * 32) + (lane & 31);
+    const int cc = c ^ ((R >> SWZ) & (CH - 1));
+    const V v = __builtin_bit_cast(V, base[(R + (lo ? BM : 0)) * CH + cc]);
+    if (a_side) {
+      if (lo) f.al[idx] = v; else f.ah[idx] = v;
+    } else {
+      if (lo) f.bl[idx] = v; else f.bh[idx] = v;
+    }
+  };
+  auto read = [&](int stage, int kk, Frag& f) {
 #pragma unroll
-  for (int q = 0; q < STAGES - 1; ++q)
-    if (q < ktiles) issue(q);
-  if (ktiles >= STAGES - 1)
-    __builtin_amdgcn_s_waitcnt(VmWait<(STAGES - 2) * LOADS>::imm);
-  else
-    __builtin_amdgcn_s_waitcnt(0);
+    for (int g = 0; g < NF; ++g) read_one(stage, kk, f, g);
+  };
+  // MFMA number q of a k step, per accumulator in the order hi*hi (A scaled
+  // by 2^t), hi*lo, lo*hi: q = prod * FM * FN + m * FN + n.
+  auto mma_one = [&](const Frag& f, V* as, int q) {
+    const int prod = q / (FM * FN), m = (q / FN) % FM, n = q % FN;
+    if (prod == 0) {
+      if (n == 0) as[m] = S::up(f.ah[m]);
+      acc[m][n] = S::mma(as[m], f.bh[n], acc[m][n]);
+    } else if (prod == 1) {
+      acc[m][n] = S::mma(f.ah[m], f.bl[n], acc[m][n]);
+    } else {
+      acc[m][n] = S::mma(f.al[m], f.bh[n], acc[m][n]);
+    }
+  };
+  // One k step of MFMAs on cur, cut into NF groups; group g also reads
+  // fragment g of nxt and, with a Fetch, issues its share of the load rounds.
+  // The fences keep that interleave: a single wave per SIMD has no other wave
+  // to cover a stall, so reads and loads go out in small doses between MFMAs.
+  auto step = [&](const Frag& cur, Frag& nxt, int rstage, int rkk, const Fetch* fetch) {
+    V as[FM];
+#pragma unroll
+    for (int g = 0; g < NF; ++g) {
+      read_one(rstage, rkk, nxt, g);
+      if (fetch) {
+#pragma unroll
+        for (int i = (g * LOADS) / NF; i < ((g + 1) * LOADS) / NF; ++i) issue_round(*fetch, i);
+      }
+#pragma unroll
+      for (int q = (g * NM) / NF; q < ((g + 1) * NM) / NF; ++q) mma_one(cur, as, q);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  // Software pipeline.  Global loads run one stage ahead; the fragments of the
+  // next k step are read from LDS while the MFMAs of the current one run.  The
+  // one barrier per k-tile sits between its two k steps: by then every wave
+  // holds the second step's fragments (its stage may be refilled) and every
+  // wave's loads of the next tile have landed (it may be read).
+  static_assert(NM >= NF, "at least one MFMA per LDS read");
+  Frag f0, f1;
+  issue(0);
+  issue(1);
+  __builtin_amdgcn_s_waitcnt(VmWait<LOADS>::imm);
   __syncthreads();
-  for (int t = 0; t < ktiles; ++t) {
-    // stage (t-1) % STAGES was released by every wave at the previous barrier
-    const bool more = t + STAGES - 1 < ktiles;
-    if (more) issue(t + STAGES - 1);
-    const u32x4* base = lds + (t % STAGES) * STAGE;
-#pragma unroll
-    for (int kk = 0; kk < BK / 16; ++kk) {
-      const int c = kk * 2 + (lane >> 5);
-      V ah[FM], al[FM], bh[FN], bl[FN];
-#pragma unroll
-      for (int m = 0; m < FM; ++m) {
-        const int R = wm * WTM + m * 32 + (lane & 31);
-        const int cc = c ^ ((R >> SWZ) & (CH - 1));
-        ah[m] = __builtin_bit_cast(V, base[R * CH + cc]);
-        al[m] = __builtin_bit_cast(V, base[(R + BM) * CH + cc]);
-      }
-#pragma unroll
-      for (int n = 0; n < FN; ++n) {
-        const int R = 2 * BM + wn * WTN + n * 32 + (lane & 31);
-        const int cc = c ^ ((R >> SWZ) & (CH - 1));
-        bh[n] = __builtin_bit_cast(V, base[R * CH + cc]);
-        bl[n] = __builtin_bit_cast(V, base[(R + BN) * CH + cc]);
-      }
-#pragma unroll
-      for (int m = 0; m < FM; ++m) {
-        const V as = S::up(ah[m]);
-#pragma unroll
-        for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(as, bh[n], acc[m][n]);
-      }
-#pragma unroll
-      for (int m = 0; m < FM; ++m)
-#pragma unroll
-        for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(ah[m], bl[n], acc[m][n]);
-#pragma unroll
-      for (int m = 0; m < FM; ++m)
-#pragma unroll
-        for (int n = 0; n < FN; ++n) acc[m][n] = S::mma(al[m], bh[n], acc[m][n]);
-    }
-    if (second && t == kt_per - 1) {
-      // S1_0 S1_0 done (scale 2^(t + 2 e1)): bring it to the scale of S S2
-#pragma unroll
-      for (int m = 0; m < FM; ++m)
-#pragma unroll
-        for (int n = 0; n < FN; ++n) acc[m][n] *= rescale;
-    }
-    // own loads of tile t+1 landed (tiles t+2 .. may stay in flight), then
-    // everyone: tile t+1 readable, stage t % STAGES free for reuse
-    if (more)
-      __builtin_amdgcn_s_waitcnt(VmWait<(STAGES - 2) * LOADS>::imm);
-    else
-      __builtin_amdgcn_s_waitcnt(0);
+  read(0, 0, f0);
+  auto body = [&](int t) {
+    // f0 was read during the previous k step and has landed: wait for it
+    // before more reads are queued (the counter cannot express "all but NF")
+    __builtin_amdgcn_s_waitcnt(LgkWait<0>::imm);
+    step(f0, f1, t & 1, 1, nullptr);
+    const Fetch fe = prep(t + 2);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    step(f1, f0, (t + 1) & 1, 0, &fe);
+  };
+  // second-order items: the S1_0 S1_0 product (scale 2^(t + 2 e1)) is brought
+  // to the scale of S S2 before the other two are accumulated
+  int t = 0;
+  const int tsplit = second ? kt_per : 0;
+  for (; t < tsplit; ++t) body(t);
+  if (second) {
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+      for (int n = 0; n < FN; ++n)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[m][n][r] *= rescale;
   }
+  for (; t < ktiles; ++t) body(t);
+  // the refetches past the end land before the LDS is reused
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
   const float scale = ldexpf(1.0f, -(S::kShift + sexp));
   const bool diag = it.ti == it.tj;
@@ -646,7 +718,7 @@ k_products_direct(const ProductArgs a) {
 
 // ------------------------------------------------------------------ dispatch
 // Tile configurations (edge, k-tile, wave grid, LDS swizzle shift).
-constexpr int kSplitBM = 256, kSplitWGM = 2, kSplitWGN = 4;
+constexpr int kSplitBM = 256, kSplitWGM = 2, kSplitWGN = 2;
 constexpr int kDirBM = 128, kDirWGM = 2, kDirWGN = 2, kDirSWZ = 1;
 constexpr int kDirBK32 = 32, kDirBK64 = 16;
 

@@ -204,7 +204,8 @@ def batch_main(args, torch, dm):
         "time_to_p1_median_ms": round(float(np.median(step_ms)), 3),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "whole batched response (algorithmic product FLOPs / step time)"},
+                     "kernel": "whole batched response (algorithmic product FLOPs / step time)",
+                     "measured_ceiling": mfma_ceiling(dm, prec, achieved)},
     }
     if not (args.no_oracle and args.no_cpu):
         # one pass of the FP64 oracle over the whole batch gives both the
@@ -238,6 +239,18 @@ def batch_main(args, torch, dm):
                           f"{len(probs)} problems of the batch: {t_or:.1f} s"}
     dm.dmpt_batch_destroy(b)
     print(json.dumps(out), flush=True)
+
+
+def mfma_ceiling(dm, precision, achieved):
+    """The split kernels' MFMA on random operands, back to back on every CU,
+    measured right after the timed steps: the rate the chip sustains at the
+    clock its power limit allows (below the data-sheet peak)."""
+    tf, ghz = dm.dmpt_probe_mfma(precision)
+    log(f"MFMA probe: {tf:.0f} TFLOP/s at {ghz:.3f} GHz; achieved/probe {achieved / tf:.3f}")
+    return {"tflops": round(tf, 1), "clock_ghz": round(ghz, 3),
+            "frac": round(achieved / tf, 4),
+            "how": "dmpt_probe_mfma: four waves per CU of independent MFMAs on random "
+                   "operands, no memory traffic"}
 
 
 def main():
@@ -333,6 +346,8 @@ def main():
                      "avg_launch_ms": round(prod_ms / max(launches, 1), 4),
                      "launches": launches},
     }
+    if args.precision.startswith("split"):
+        out["roofline"]["measured_ceiling"] = mfma_ceiling(dm, args.precision, achieved)
     # the observable of the response (the polarisability-type contraction)
     pi = dm.dmpt_contract(H1s, P1s)
     out["observable"] = {"tr_h1_p1": [float(pi[j, j]) for j in range(len(H1s))]}

@@ -27,7 +27,7 @@ EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_re
            "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
            "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
-           "dmpt_selftest_mfma"]
+           "dmpt_selftest_mfma", "dmpt_probe_mfma"]
 
 
 class DmptOptions(ctypes.Structure):
@@ -138,6 +138,8 @@ def _load():
     lib.dmpt_gershgorin.restype = c_int32
     lib.dmpt_selftest_mfma.argtypes = [POINTER(c_int32), c_void_p]
     lib.dmpt_selftest_mfma.restype = c_int32
+    lib.dmpt_probe_mfma.argtypes = [c_int32, POINTER(c_double), POINTER(c_double), c_void_p]
+    lib.dmpt_probe_mfma.restype = c_int32
     return lib
 
 
@@ -359,6 +361,13 @@ def dmpt_gershgorin(H, stream=None):
     eps = (c_double * 2)()
     _check(LIB.dmpt_gershgorin(_dev(H, "H"), H.shape[0], eps, _stream(stream)))
     return float(eps[0]), float(eps[1])
+
+
+def dmpt_probe_mfma(precision: str = "split_fp16", stream=None):
+    """dmpt_probe_mfma: (TFLOP/s, shader GHz) of back-to-back MFMAs on random operands."""
+    tf, ghz = c_double(0.0), c_double(0.0)
+    _check(LIB.dmpt_probe_mfma(PRECISION[precision], byref(tf), byref(ghz), _stream(stream)))
+    return tf.value, ghz.value
 
 
 def dmpt_selftest_mfma(stream=None) -> int:

@@ -925,6 +925,48 @@ dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps, void* strea
   return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
 }
 
+dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz, void* stream) {
+  if (precision != DMPT_SPLIT_FP16 && precision != DMPT_SPLIT_BF16)
+    return fail(DMPT_ENOTSUP, "the probe runs the split precisions' MFMA only");
+  hipStream_t s = (hipStream_t)stream;
+  const int blocks = device_cu_count(), iters = 20000;
+  int dev = 0, wall_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      wall_khz <= 0)
+    return fail(DMPT_EHIP, "wall-clock rate unavailable");
+  float* out = nullptr;
+  int64_t* ticks = nullptr;
+  if (hipMalloc((void**)&out, (size_t)blocks * 4 * kWave * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&ticks, 2 * sizeof(int64_t)) != hipSuccess) {
+    hipFree(out);
+    return fail(DMPT_ENOMEM, "allocation failed");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  // one launch to settle the clock, then the timed one
+  float ms = 0.0f;
+  int64_t t[2] = {0, 0};
+  for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+    e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_mfma_rate((dmpt_precision)precision, blocks, iters, out, ticks, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  }
+  if (e == hipSuccess) e = hipMemcpy(t, ticks, sizeof(t), hipMemcpyDeviceToHost);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(out);
+  hipFree(ticks);
+  if (e != hipSuccess) return fail(DMPT_EHIP, hipGetErrorString(e));
+  const double flops = (double)blocks * 4 * iters * 48 * (2.0 * 32 * 32 * 16);
+  if (tflops) *tflops = ms > 0.0f ? flops / (ms * 1e-3) / 1e12 : 0.0;
+  if (clock_ghz) *clock_ghz = t[1] > 0 ? (double)t[0] / ((double)t[1] / (wall_khz * 1e3)) / 1e9 : 0.0;
+  return DMPT_OK;
+}
+
 dmpt_status dmpt_selftest_mfma(int32_t* detail, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   int32_t* dev = nullptr;

@@ -961,4 +961,67 @@ hipError_t launch_selftest_mfma(int32_t* result, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ MFMA rate probe
+// Four waves per CU issue independent 32x32x16 MFMAs (eight accumulators, 48
+// per iteration) on pseudo-random operands in [-1, 1), with no memory traffic.
+// The chip's power management sets the clock from the switching activity, so
+// random operands give the clock the product kernels run at.  Workgroup 0
+// records the shader-clock (s_memtime) and wall-clock (s_memrealtime) ticks
+// it spent; every lane stores its accumulator sum so that nothing is elided.
+template <typename T16>
+__global__ void __launch_bounds__(4 * kWave) k_mfma_rate(float* out, int64_t* ticks, int iters) {
+  using S = Split16<T16>;
+  typename S::V a, b;
+  for (int e = 0; e < 8; ++e) {
+    uint32_t h = (uint32_t)(threadIdx.x * 8 + e + 1) * 2654435761u + blockIdx.x * 40503u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    a[e] = (T16)((float)(h & 0xffff) * (2.0f / 65536.0f) - 1.0f);
+    b[e] = (T16)((float)(h >> 16) * (2.0f / 65536.0f) - 1.0f);
+  }
+  f32x16 acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[j][r] = 0.0f;
+  const int64_t c0 = __builtin_amdgcn_s_memtime(), w0 = __builtin_amdgcn_s_memrealtime();
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int rep = 0; rep < 6; ++rep)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = S::mma(a, b, acc[j]);
+  }
+  const int64_t c1 = __builtin_amdgcn_s_memtime(), w1 = __builtin_amdgcn_s_memrealtime();
+  float sum = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sum += acc[j][r];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = sum;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ticks[0] = c1 - c0;
+    ticks[1] = w1 - w0;
+  }
+}
+
+hipError_t launch_mfma_rate(dmpt_precision prec, int blocks, int iters, float* out,
+                            int64_t* ticks, hipStream_t s) {
+  // one workgroup per CU: the LDS request leaves room for no second one
+  constexpr size_t lds = 96 * 1024;
+  const void* k = prec == DMPT_SPLIT_BF16 ? (const void*)k_mfma_rate<__bf16>
+                                          : (const void*)k_mfma_rate<_Float16>;
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (prec == DMPT_SPLIT_BF16)
+    hipLaunchKernelGGL(k_mfma_rate<__bf16>, dim3(blocks), dim3(4 * kWave), lds, s, out, ticks,
+                       iters);
+  else
+    hipLaunchKernelGGL(k_mfma_rate<_Float16>, dim3(blocks), dim3(4 * kWave), lds, s, out, ticks,
+                       iters);
+  return hipGetLastError();
+}
+
+int device_cu_count() { return device_cus(); }
+
 }  // namespace dmpt

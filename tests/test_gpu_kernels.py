@@ -23,6 +23,24 @@ def test_mfma_lane_layouts(dm):
     assert dm.dmpt_selftest_mfma() == 0
 
 
+@pytest.mark.parametrize("precision", ["split_fp16", "split_bf16"])
+def test_mfma_rate_probe(dm, precision):
+    """The probe's rate stays below the data-sheet dense peak (2.5 PFLOP/s) and
+    is consistent with its own clock reading: at most 1024 flops per clock per
+    SIMD, 4 SIMDs on each of 256 CUs."""
+    tf, ghz = dm.dmpt_probe_mfma(precision)
+    print(f"{precision} MFMA probe: {tf:.0f} TFLOP/s at {ghz:.3f} GHz", flush=True)
+    assert 0.5 < ghz < 3.0
+    assert 100.0 < tf <= 2516.0 * 1.01
+    assert tf <= 1024 * 4 * 256 * ghz * 1e-3 * 1.02
+
+
+def test_mfma_rate_probe_rejects_other_precisions(dm):
+    with pytest.raises(dm.DmptError) as ei:
+        dm.dmpt_probe_mfma("fp64")
+    assert ei.value.status == -7
+
+
 @pytest.mark.parametrize("n", [37, 300, 1000])
 def test_gershgorin_matches_numpy(dm, n):
     from oracle.exact import gershgorin

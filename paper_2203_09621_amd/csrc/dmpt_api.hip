@@ -83,6 +83,50 @@ std::vector<TileItem> build_items(int T, int k) {
   return v;
 }
 
+// Order of the items of a persistent launch on `grid` workgroups, where item
+// r * grid + s runs on slot s.  Items are dealt in list order (responses,
+// two products per tile, before X = S^2, one product), round by round; a
+// slot that would pass the target cost max(ceil(total / grid), largest item)
+// takes a placeholder (out = -1, skipped at once) and the item waits for the
+// next slot.  Every slot then ends within one item of the mean, where plain
+// dealing leaves the slots that drew an extra response tile an extra X tile
+// as well.  Lists of at most `grid` items need no rounds and stay as they are.
+std::vector<TileItem> balanced_rounds(const std::vector<TileItem>& items, int grid) {
+  const int n = (int)items.size();
+  if (n <= grid) return items;
+  auto cost = [](const TileItem& it) { return it.out == 0 ? 1 : 2; };
+  int64_t total = 0;
+  int biggest = 1;
+  for (const TileItem& it : items) {
+    total += cost(it);
+    biggest = std::max(biggest, cost(it));
+  }
+  int64_t target = std::max<int64_t>((total + grid - 1) / grid, biggest);
+  std::vector<int64_t> load(grid, 0);
+  std::vector<TileItem> out;
+  TileItem hole;
+  hole.out = -1;
+  hole.prob = 0;
+  hole.ti = hole.tj = 0;
+  int pos = 0;
+  while (pos < n) {
+    bool placed = false;
+    for (int s = 0; s < grid && pos < n; ++s) {
+      const int c = cost(items[pos]);
+      if (load[s] + c <= target) {
+        out.push_back(items[pos++]);
+        load[s] += c;
+        placed = true;
+      } else {
+        out.push_back(hole);
+      }
+    }
+    if (!placed) ++target;
+  }
+  while (!out.empty() && out.back().out < 0) out.pop_back();
+  return out;
+}
+
 // Items of outputs 1 .. m only (no X = S^2): the adjoint products.
 std::vector<TileItem> build_items_outputs(int T, int m) {
   std::vector<TileItem> all = build_items(T, m), v;
@@ -337,8 +381,15 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
     }
   }
   const int T = (int)(c->np / tile);
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
   for (int k = 1; k <= k_max; ++k) {
-    std::vector<TileItem> items = build_items(T, k);
+    // split forms: one workgroup per CU in the fused launch, rounds balanced
+    std::vector<TileItem> items = split ? balanced_rounds(build_items(T, k), cus)
+                                        : build_items(T, k);
     c->n_items[k] = (int)items.size();
     get((void**)&c->items[k], items.size() * sizeof(TileItem));
     if (e == hipSuccess)

@@ -84,7 +84,7 @@ struct LayerState {
 // One output tile of a layer product.  out = 0: X = S^2; out = 1 + j: X1_j,
 // or X2 = S1_0 S1_0 + S S2 + S2 S when j is the state's second-order slot.
 struct TileItem {
-  int16_t out;
+  int16_t out;               // 0: X, 1 + j: response j; < 0: placeholder, skipped
   int16_t prob;              // problem index (batched launches; 0 otherwise)
   int32_t ti, tj;            // tile row/col (ti <= tj)
 };

@@ -76,6 +76,7 @@ template <> struct Split16<__bf16> {
 // layer itself, for ||S - X||_F.
 template <bool FUSED>
 __device__ __forceinline__ bool item_active(const ProductArgs& a, const TileItem& it, int* sexp) {
+  if (it.out < 0) return false;                 // placeholder of a balanced round
   const LayerState* st = FUSED ? a.probs[it.prob].state : a.state;
   if (st) {
     if (st->done) return false;

@@ -30,6 +30,39 @@ dmpt_status fail(dmpt_status s, const std::string& msg) {
 
 void dmpt::set_last_error(const char* msg) { g_err = msg; }
 
+std::vector<int32_t> dmpt::balanced_rounds(const std::vector<int64_t>& cost, int grid,
+                                           size_t limit) {
+  const int n = (int)cost.size();
+  std::vector<int32_t> plain(n);
+  for (int i = 0; i < n; ++i) plain[i] = i;
+  if (n <= grid || grid <= 0) return plain;
+  int64_t total = 0, biggest = 1;
+  for (int64_t c : cost) {
+    total += c;
+    biggest = std::max(biggest, c);
+  }
+  int64_t target = std::max<int64_t>((total + grid - 1) / grid, biggest);
+  std::vector<int64_t> load(grid, 0);
+  std::vector<int32_t> out;
+  int pos = 0;
+  while (pos < n) {
+    bool placed = false;
+    for (int s = 0; s < grid && pos < n; ++s) {
+      if (load[s] + cost[pos] <= target) {
+        load[s] += cost[pos];
+        out.push_back(pos++);
+        placed = true;
+      } else {
+        out.push_back(-1);
+      }
+    }
+    if (out.size() > limit) return plain;
+    if (!placed) ++target;
+  }
+  while (!out.empty() && out.back() < 0) out.pop_back();
+  return out;
+}
+
 namespace {
 
 #define HIPCHK(expr)                                                                     \
@@ -83,47 +116,21 @@ std::vector<TileItem> build_items(int T, int k) {
   return v;
 }
 
-// Order of the items of a persistent launch on `grid` workgroups, where item
-// r * grid + s runs on slot s.  Items are dealt in list order (responses,
-// two products per tile, before X = S^2, one product), round by round; a
-// slot that would pass the target cost max(ceil(total / grid), largest item)
-// takes a placeholder (out = -1, skipped at once) and the item waits for the
-// next slot.  Every slot then ends within one item of the mean, where plain
-// dealing leaves the slots that drew an extra response tile an extra X tile
-// as well.  Lists of at most `grid` items need no rounds and stay as they are.
-std::vector<TileItem> balanced_rounds(const std::vector<TileItem>& items, int grid) {
-  const int n = (int)items.size();
-  if (n <= grid) return items;
-  auto cost = [](const TileItem& it) { return it.out == 0 ? 1 : 2; };
-  int64_t total = 0;
-  int biggest = 1;
-  for (const TileItem& it : items) {
-    total += cost(it);
-    biggest = std::max(biggest, cost(it));
-  }
-  int64_t target = std::max<int64_t>((total + grid - 1) / grid, biggest);
-  std::vector<int64_t> load(grid, 0);
-  std::vector<TileItem> out;
-  TileItem hole;
-  hole.out = -1;
-  hole.prob = 0;
-  hole.ti = hole.tj = 0;
-  int pos = 0;
-  while (pos < n) {
-    bool placed = false;
-    for (int s = 0; s < grid && pos < n; ++s) {
-      const int c = cost(items[pos]);
-      if (load[s] + c <= target) {
-        out.push_back(items[pos++]);
-        load[s] += c;
-        placed = true;
-      } else {
-        out.push_back(hole);
-      }
+// Single-problem lists: response tiles cost two products, tiles of X one.
+std::vector<TileItem> balanced_items(const std::vector<TileItem>& items, int grid) {
+  std::vector<int64_t> cost(items.size());
+  for (size_t i = 0; i < items.size(); ++i) cost[i] = items[i].out == 0 ? 1 : 2;
+  const std::vector<int32_t> order = balanced_rounds(cost, grid, 2 * items.size());
+  std::vector<TileItem> out(order.size());
+  for (size_t q = 0; q < order.size(); ++q) {
+    if (order[q] >= 0) {
+      out[q] = items[order[q]];
+    } else {
+      out[q].out = -1;
+      out[q].prob = 0;
+      out[q].ti = out[q].tj = 0;
     }
-    if (!placed) ++target;
   }
-  while (!out.empty() && out.back().out < 0) out.pop_back();
   return out;
 }
 
@@ -388,7 +395,7 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
     cus = 256;
   for (int k = 1; k <= k_max; ++k) {
     // split forms: one workgroup per CU in the fused launch, rounds balanced
-    std::vector<TileItem> items = split ? balanced_rounds(build_items(T, k), cus)
+    std::vector<TileItem> items = split ? balanced_items(build_items(T, k), cus)
                                         : build_items(T, k);
     c->n_items[k] = (int)items.size();
     get((void**)&c->items[k], items.size() * sizeof(TileItem));

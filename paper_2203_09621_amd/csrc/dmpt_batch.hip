@@ -297,6 +297,7 @@ struct dmpt_batch {
   TileItem* items[2] = {nullptr, nullptr};     // [0]: 256-row tiles, [1]: 128-row tiles
   int n_items[2] = {0, 0};
   int total_k = 0;
+  int cus = 256;                               // compute units of the device
   const double** h0tab = nullptr;
   const double** h1tab = nullptr;
   double** p0tab = nullptr;
@@ -340,18 +341,59 @@ void batch_free(dmpt_batch* b) {
 // item range, and the per-problem buffer descriptors (the k extent follows
 // the class).
 hipError_t build_class_items(dmpt_batch* b, int threshold) {
+  // Per class: problems in order of decreasing cost (products times k-tiles
+  // over their tiles), their items dealt in balanced rounds over the launch's
+  // workgroups.  Each problem's items stay in order and contiguous apart from
+  // placeholders, which the kernels and the decisions skip.
   std::vector<TileItem> cls[2];
   std::vector<int> first(b->count), count(b->count), which(b->count);
+  std::vector<std::vector<TileItem>> own(b->count);
+  std::vector<std::vector<int64_t>> own_cost(b->count);
+  std::vector<int64_t> total(b->count, 0);
   for (int p = 0; p < b->count; ++p) {
     const BatchProblem& bp = b->hp[p];
     const int c = bp.np <= threshold ? 1 : 0;
     const int tile = c ? 128 : 256;
     const int T = (int)((bp.n + tile - 1) / tile);
-    std::vector<TileItem> v = triangle_items(T, bp.k, p);
     which[p] = c;
-    first[p] = (int)cls[c].size();
-    count[p] = (int)v.size();
-    cls[c].insert(cls[c].end(), v.begin(), v.end());
+    own[p] = triangle_items(T, bp.k, p);
+    for (const TileItem& it : own[p]) {
+      own_cost[p].push_back((it.out == 0 ? 1 : 2) * ((int64_t)T * tile / kPanelK));
+      total[p] += own_cost[p].back();
+    }
+  }
+  for (int c = 0; c < 2; ++c) {
+    std::vector<int> probs;
+    for (int p = 0; p < b->count; ++p)
+      if (which[p] == c) probs.push_back(p);
+    std::stable_sort(probs.begin(), probs.end(), [&](int x, int y) { return total[x] > total[y]; });
+    std::vector<TileItem> list;
+    std::vector<int64_t> cost;
+    for (int p : probs) {
+      list.insert(list.end(), own[p].begin(), own[p].end());
+      cost.insert(cost.end(), own_cost[p].begin(), own_cost[p].end());
+    }
+    const int cap = (c ? 2 : 1) * b->cus;
+    const int grid = (int)std::min<size_t>(list.size(), (size_t)cap);
+    const std::vector<int32_t> order = balanced_rounds(cost, grid, 2 * list.size());
+    std::vector<int> lo(b->count, -1), hi(b->count, -1);
+    for (size_t q = 0; q < order.size(); ++q) {
+      TileItem it;
+      if (order[q] >= 0) {
+        it = list[order[q]];
+        if (lo[it.prob] < 0) lo[it.prob] = (int)q;
+        hi[it.prob] = (int)q;
+      } else {
+        it.out = -1;
+        it.prob = 0;
+        it.ti = it.tj = 0;
+      }
+      cls[c].push_back(it);
+    }
+    for (int p : probs) {
+      first[p] = lo[p];
+      count[p] = hi[p] - lo[p] + 1;
+    }
   }
   b->threshold = threshold;
   b->n_items[0] = (int)cls[0].size();
@@ -521,6 +563,13 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
   b->max_layers = opt.max_layers;
   b->use_graph = opt.graph;
   b->stream = (hipStream_t)stream;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      b->cus = cus;
+  }
   auto bail = [&](dmpt_status s, const std::string& m) {
     batch_free(b);
     return bfail(s, m);
@@ -583,10 +632,11 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
     n_big += (size_t)(1 + q.k) * Tb * (Tb + 1) / 2;
     n_small += (size_t)(1 + q.k) * Ts * (Ts + 1) / 2;
   }
-  get((void**)&b->items[0], sizeof(TileItem) * n_big);
-  get((void**)&b->items[1], sizeof(TileItem) * n_small);
-  get((void**)&b->part_f, sizeof(double) * (n_big + n_small));
-  get((void**)&b->part_m, sizeof(double) * (n_big + n_small));
+  // balanced rounds add placeholders: at most as many as there are items
+  get((void**)&b->items[0], sizeof(TileItem) * 2 * n_big);
+  get((void**)&b->items[1], sizeof(TileItem) * 2 * n_small);
+  get((void**)&b->part_f, sizeof(double) * 2 * (n_big + n_small));
+  get((void**)&b->part_m, sizeof(double) * 2 * (n_big + n_small));
   get((void**)&b->h0tab, sizeof(void*) * count);
   get((void**)&b->p0tab, sizeof(void*) * count);
   get((void**)&b->h1tab, sizeof(void*) * h1);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "dmpt.h"
 
@@ -145,6 +146,15 @@ struct ProductArgs {
 // ----------------------------------------------------------------- launchers
 // layer products (kernels_gemm.hip)
 int product_tile(dmpt_precision prec);   // output tile edge used by the product kernels
+// Order of n items (cost[i]: products times k-tiles) for a persistent launch
+// on `grid` workgroups, where position r * grid + s runs on slot s.  Items
+// keep their list order and are dealt round by round against a target cost
+// max(ceil(total / grid), largest item); a slot that would pass it takes a
+// placeholder (-1, skipped at once) and the item waits for the next slot, so
+// that every slot ends within one item of the mean.  Returns, per position,
+// the item index or -1; the plain order when n <= grid or when the result
+// would exceed `limit` positions.
+std::vector<int32_t> balanced_rounds(const std::vector<int64_t>& cost, int grid, size_t limit);
 hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_t s);
 // Tile items of an Np x Np output for the single-product modes: upper tiles
 // (mode 1) or all tiles (mode 2), tile edge product_tile(prec).

@@ -146,6 +146,89 @@ def cpu_baseline(p, workload, layers):
             "seconds_full_estimate": t_full}
 
 
+def adjoint_main(args, torch, dm):
+    """Configuration 5: N = 4096 forward (split BF16, checkpoints every 8 layers)
+    and the hand-written adjoint (FP32 products) of L = Tr(P1 W), timed together
+    as one step; gradients against the oracle's closed form."""
+    from workloads import config5
+    prec = args.precision or "split_bf16"
+    p = config5()
+    dev = torch.device("cuda:0")
+    H0 = torch.from_numpy(p.H0).to(dev)
+    H1 = torch.from_numpy(p.H1[0]).to(dev)
+    W = torch.from_numpy(p.W).to(dev)
+    P0, P1 = torch.empty_like(H0), torch.empty_like(H0)
+    g0, g1 = torch.empty_like(H0), torch.empty_like(H0)
+    ctx = dm.dmpt_init(H0, p.nocc, k_max=1, precision=prec, timing=True, ckpt_every=8)
+
+    def step():
+        dm.dmpt_set_hamiltonian(ctx, H0)
+        st = dm.dmpt_response(ctx, [H1], P0, [P1])[2]
+        ast = dm.dmpt_adjoint(ctx, [W], g0, [g1])[2]
+        return st, ast
+
+    for w in range(args.warmup):
+        st, ast = step()
+        log(f"warmup {w}: forward {st['ms']:.1f} ms ({st['layers']} layers), adjoint {ast['ms']:.1f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    st, ast = runs[-1]
+    fwd_ms = float(np.mean([r[0]["ms"] for r in runs]))
+    adj_ms = float(np.mean([r[1]["ms"] for r in runs]))
+    layers = st["layers"]
+    log(f"timed {args.steps} steps: {ms:.1f} ms/step (forward {fwd_ms:.1f}, adjoint {adj_ms:.1f})")
+    # reverse layers: T2 = S Sh + Sh S, T1 = S Sh1 + Sh1 S, T3 = Sh1 S1 + S1 Sh1 in
+    # FP32, N^3 multiply-adds each (symmetric, upper tiles); the recomputation of
+    # the forward layers comes on top, so this is a lower bound on the rate
+    rev = 2.0 * 3 * p.N ** 3 * layers
+    achieved = rev / (adj_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(1e3 / ms, 4),
+        "unit": "gradient evaluations/s (forward + adjoint of L = Tr(P1 W), N = 4096)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"split_bf16": "bf16", "split_fp16": "f16", "fp32": "f32", "fp64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": p.name, "N": p.N, "nocc": p.nocc, "forward_precision": prec,
+                   "adjoint_products": "f32" if prec != "fp64" else "f64",
+                   "checkpoint_every": 8, "layers": layers},
+        "forward_ms": round(fwd_ms, 3), "adjoint_ms": round(adj_ms, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
+                     "peak": PEAK_TFLOPS["fp32" if prec != "fp64" else "fp64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS["fp32" if prec != "fp64" else "fp64"], 4),
+                     "traffic": None,
+                     "kernel": "adjoint reverse products (FP32 MFMA) over the whole adjoint "
+                               "time, recomputation included: a lower bound"},
+    }
+    if not (args.no_oracle and args.no_cpu):
+        from oracle import adjoint
+        t = time.perf_counter()
+        r1 = adjoint.grad_h1(p.H0, [p.W], p.nocc)[0]
+        r0 = adjoint.grad_h0(p.H0, p.H1, [p.W], p.nocc)
+        t_or = time.perf_counter() - t
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        e0, e1 = rel(g0.cpu().numpy(), r0), rel(g1.cpu().numpy(), r1)
+        log(f"oracle gradients: {t_or:.1f} s; errors dH0 {e0:.2e} dH1 {e1:.2e}")
+        if not args.no_oracle:
+            out["rel_fro_err"] = {"dL_dH0": e0, "dL_dH1": e1}
+        if not args.no_cpu:
+            cores = os.cpu_count()
+            try:
+                from threadpoolctl import threadpool_info
+                cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+            except Exception:  # pragma: no cover
+                pass
+            out["cpu_baseline"] = {"value": round(1.0 / t_or, 4), "unit": out["unit"],
+                                   "cores": cores, "kind": "oracle",
+                                   "sample": f"closed-form FP64 gradients (eigh + divided "
+                                             f"differences) at N = {p.N}: {t_or:.1f} s"}
+    dm.dmpt_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
 def batch_main(args, torch, dm):
     """Batched workload: one step = dmpt_batch_response over the 512 problems."""
     from workloads import config4
@@ -258,7 +341,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=list(PEAK_TFLOPS))
     ap.add_argument("--batch-layers", type=int, default=100,
                     help="layers captured in the batched graph (c4)")
@@ -279,6 +362,8 @@ def main():
         if args.precision is None:
             args.precision = "split_bf16"
         return batch_main(args, torch, dm)
+    if args.workload == "c5":
+        return adjoint_main(args, torch, dm)
     if args.precision is None:
         args.precision = "split_fp16"
     t = time.perf_counter()

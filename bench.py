@@ -201,7 +201,9 @@ def adjoint_main(args, torch, dm):
                      "frac": round(achieved / PEAK_TFLOPS["fp32" if prec != "fp64" else "fp64"], 4),
                      "traffic": None,
                      "kernel": "adjoint reverse products (FP32 MFMA) over the whole adjoint "
-                               "time, recomputation included: a lower bound"},
+                               "time, recomputation included: a lower bound",
+                     "measured_ceiling": mfma_ceiling(dm, "fp32" if prec != "fp64" else "fp64",
+                                                      achieved)},
     }
     if not (args.no_oracle and args.no_cpu):
         from oracle import adjoint
@@ -454,10 +456,12 @@ def main():
         torch.cuda.synchronize()
         ms64 = (time.perf_counter() - ta) * 1e3
         alg64 = algorithmic_flops(p.N, k_active(s64), s64["x_layers"], "fp64")
+        tf64 = alg64 / (s64["product_ms"] * 1e-3) / 1e12
         out["fp64_gpu"] = {"ms": round(ms64, 2), "layers": s64["layers"],
                            "speedup_of_split": round(ms64 / ms, 2),
-                           "mfma_tflops": round(alg64 / (s64["product_ms"] * 1e-3) / 1e12, 2),
-                           "peak": PEAK_TFLOPS["fp64"]}
+                           "mfma_tflops": round(tf64, 2),
+                           "peak": PEAK_TFLOPS["fp64"],
+                           "measured_ceiling": mfma_ceiling(dm, "fp64", tf64)}
         log(f"fp64 GPU form: {ms64:.1f} ms, layers {s64['layers']}, speedup {ms64 / ms:.2f}x")
         dm.dmpt_destroy(c64)
     if ctx is not None:

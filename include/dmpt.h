@@ -278,15 +278,16 @@ dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps /* host, 2 *
  * mismatching instructions. */
 dmpt_status dmpt_selftest_mfma(int32_t* detail, void* stream);
 
-/* Sustained rate of the MFMA instruction the split forms use (32x32x16 FP16
- * for DMPT_SPLIT_FP16, BF16 for DMPT_SPLIT_BF16): four waves on every CU issue
+/* Sustained rate of the MFMA instruction a precision's product kernels use
+ * (32x32x16 FP16 for DMPT_SPLIT_FP16, BF16 for DMPT_SPLIT_BF16, 16x16x4 FP32
+ * for DMPT_FP32, FP64 for DMPT_FP64): four waves on every CU issue
  * independent MFMAs on pseudo-random operands, without memory traffic, for
- * about 20 ms (after one settling launch).  tflops (host, may be NULL)
- * receives the rate at 2 flops per multiply-add, clock_ghz (host, may be
- * NULL) the shader clock workgroup 0 saw.  Under such a load the chip lowers
- * its clock to stay within its power limit, so this is the ceiling the
+ * tens of milliseconds (after one settling launch).  tflops (host, may be
+ * NULL) receives the rate at 2 flops per multiply-add, clock_ghz (host, may
+ * be NULL) the shader clock workgroup 0 saw.  Under such a load the chip
+ * lowers its clock to stay within its power limit, so this is the ceiling the
  * product kernels can approach on the device, below the data-sheet peak.
- * Errors: ENOTSUP (other precisions), ENOMEM, EHIP. */
+ * Errors: EINVAL (unknown precision), ENOMEM, EHIP. */
 dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz, void* stream);
 
 #ifdef __cplusplus

@@ -364,7 +364,8 @@ def dmpt_gershgorin(H, stream=None):
 
 
 def dmpt_probe_mfma(precision: str = "split_fp16", stream=None):
-    """dmpt_probe_mfma: (TFLOP/s, shader GHz) of back-to-back MFMAs on random operands."""
+    """dmpt_probe_mfma: (TFLOP/s, shader GHz) of back-to-back MFMAs on random operands,
+    for the MFMA instruction of `precision`'s product kernels."""
     tf, ghz = c_double(0.0), c_double(0.0)
     _check(LIB.dmpt_probe_mfma(PRECISION[precision], byref(tf), byref(ghz), _stream(stream)))
     return tf.value, ghz.value

@@ -984,8 +984,8 @@ dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps, void* strea
 }
 
 dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz, void* stream) {
-  if (precision != DMPT_SPLIT_FP16 && precision != DMPT_SPLIT_BF16)
-    return fail(DMPT_ENOTSUP, "the probe runs the split precisions' MFMA only");
+  if (precision < DMPT_FP64 || precision > DMPT_SPLIT_FP16)
+    return fail(DMPT_EINVAL, "unknown precision");
   hipStream_t s = (hipStream_t)stream;
   const int blocks = device_cu_count(), iters = 20000;
   int dev = 0, wall_khz = 0;
@@ -1019,7 +1019,7 @@ dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz
   hipFree(out);
   hipFree(ticks);
   if (e != hipSuccess) return fail(DMPT_EHIP, hipGetErrorString(e));
-  const double flops = (double)blocks * 4 * iters * 48 * (2.0 * 32 * 32 * 16);
+  const double flops = (double)blocks * 4 * iters * 48 * mfma_probe_flops((dmpt_precision)precision);
   if (tflops) *tflops = ms > 0.0f ? flops / (ms * 1e-3) / 1e12 : 0.0;
   if (clock_ghz) *clock_ghz = t[1] > 0 ? (double)t[0] / ((double)t[1] / (wall_khz * 1e3)) / 1e9 : 0.0;
   return DMPT_OK;

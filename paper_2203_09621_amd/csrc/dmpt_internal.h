@@ -234,10 +234,12 @@ hipError_t launch_adj_out(dmpt_precision prec, const LayerState* fwd, const void
                           double* dst, int64_t n, hipStream_t s);
 hipError_t launch_selftest_mfma(int32_t* result, hipStream_t s);
 // MFMA rate probe: `blocks` workgroups of four waves, `iters` x 48 MFMAs each
-// (32x32x16 f16, or bf16 for DMPT_SPLIT_BF16); out[blocks * 256] receives
-// per-lane sums, ticks[2] the shader-clock and wall-clock ticks of workgroup 0.
+// (32x32x16 f16 or bf16 for the split precisions, 16x16x4 f32 or f64 for the
+// direct ones); out[blocks * 256] receives per-lane sums, ticks[2] the
+// shader-clock and wall-clock ticks of workgroup 0.
 hipError_t launch_mfma_rate(dmpt_precision prec, int blocks, int iters, float* out,
                             int64_t* ticks, hipStream_t s);
+double mfma_probe_flops(dmpt_precision prec);   // flops of one MFMA of the probe
 int device_cu_count();   // compute units of the current device (256 if unknown)
 
 // Record the reason of a non-OK status for dmpt_last_error (dmpt_api.hip).

@@ -675,18 +675,25 @@ k_products_direct(const ProductArgs a) {
         const int R = BM + wn * WTN + n * 16 + (lane & 15);
         bf[n] = base[R * CH + (c ^ ((R >> SWZ) & (CH - 1)))];
       }
+      // Accumulators in groups of GRP, each group through all E elements
+      // before the next: the FP64 16x16x4 MFMA keeps about 90% of its rate
+      // with four accumulators in turn and 72% with sixteen (FP32 keeps full
+      // rate either way).  Every accumulator still takes its k in order.
+      constexpr int GRP = sizeof(T) == 8 ? 4 : FM * FN;
+      static_assert((FM * FN) % GRP == 0, "whole groups");
+      typedef T TV __attribute__((ext_vector_type(E)));
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
+      for (int g0 = 0; g0 < FM * FN; g0 += GRP) {
 #pragma unroll
-        for (int m = 0; m < FM; ++m) {
-          typedef T TV __attribute__((ext_vector_type(E)));
-          const T av = __builtin_bit_cast(TV, af[m])[e];
+        for (int e = 0; e < E; ++e)
 #pragma unroll
-          for (int n = 0; n < FN; ++n) {
-            const T bv = __builtin_bit_cast(TV, bf[n])[e];
-            acc[m][n] = D::mma(av, bv, acc[m][n]);
+          for (int q = g0; q < g0 + GRP; ++q) {
+            const int m = q / FN, n = q % FN;
+            acc[m][n] = D::mma(__builtin_bit_cast(TV, af[m])[e], __builtin_bit_cast(TV, bf[n])[e],
+                               acc[m][n]);
           }
-        }
+        // (the scheduler would interleave the groups again)
+        if constexpr (GRP < FM * FN) __builtin_amdgcn_sched_barrier(0);
       }
     }
     if (t + 1 < ktiles) lstore(cur ^ 1);
@@ -1006,20 +1013,85 @@ __global__ void __launch_bounds__(4 * kWave) k_mfma_rate(float* out, int64_t* ti
   }
 }
 
+// The same for the direct forms' 16x16x4 FP32 / FP64 MFMA, 48 MFMAs per
+// iteration.  FP64 runs four accumulators: measured on gfx950, its 16x16x4
+// MFMA sustains about 90% of the data-sheet rate with four accumulators in
+// turn, 83% with eight and 72% with sixteen; FP32 keeps full rate with
+// sixteen.
+template <typename T>
+__global__ void __launch_bounds__(4 * kWave) k_mfma_rate_direct(float* out, int64_t* ticks,
+                                                                int iters) {
+  using D = Direct<T>;
+  constexpr int NACC = sizeof(T) == 8 ? 4 : 16;
+  uint32_t h = (uint32_t)(threadIdx.x + 1) * 2654435761u + blockIdx.x * 40503u;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  const T a = (T)((float)(h & 0xffff) * (2.0f / 65536.0f) - 1.0f);
+  const T b = (T)((float)(h >> 16) * (2.0f / 65536.0f) - 1.0f);
+  typename D::Acc acc[NACC];
+#pragma unroll
+  for (int j = 0; j < NACC; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[j][r] = (T)0;
+  const int64_t c0 = __builtin_amdgcn_s_memtime(), w0 = __builtin_amdgcn_s_memrealtime();
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int rep = 0; rep < 48 / NACC; ++rep)
+#pragma unroll
+      for (int j = 0; j < NACC; ++j) acc[j] = D::mma(a, b, acc[j]);
+  }
+  const int64_t c1 = __builtin_amdgcn_s_memtime(), w1 = __builtin_amdgcn_s_memrealtime();
+  T sum = (T)0;
+#pragma unroll
+  for (int j = 0; j < NACC; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum += acc[j][r];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = (float)sum;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ticks[0] = c1 - c0;
+    ticks[1] = w1 - w0;
+  }
+}
+
+double mfma_probe_flops(dmpt_precision prec) {
+  // flops of one MFMA of the probe: 32x32x16 for the split forms, 16x16x4 else
+  return (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16) ? 2.0 * 32 * 32 * 16
+                                                              : 2.0 * 16 * 16 * 4;
+}
+
 hipError_t launch_mfma_rate(dmpt_precision prec, int blocks, int iters, float* out,
                             int64_t* ticks, hipStream_t s) {
   // one workgroup per CU: the LDS request leaves room for no second one
   constexpr size_t lds = 96 * 1024;
-  const void* k = prec == DMPT_SPLIT_BF16 ? (const void*)k_mfma_rate<__bf16>
-                                          : (const void*)k_mfma_rate<_Float16>;
+  const void* k = nullptr;
+  switch (prec) {
+    case DMPT_SPLIT_BF16: k = (const void*)k_mfma_rate<__bf16>; break;
+    case DMPT_SPLIT_FP16: k = (const void*)k_mfma_rate<_Float16>; break;
+    case DMPT_FP32: k = (const void*)k_mfma_rate_direct<float>; break;
+    case DMPT_FP64: k = (const void*)k_mfma_rate_direct<double>; break;
+  }
+  if (!k) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (prec == DMPT_SPLIT_BF16)
-    hipLaunchKernelGGL(k_mfma_rate<__bf16>, dim3(blocks), dim3(4 * kWave), lds, s, out, ticks,
-                       iters);
-  else
-    hipLaunchKernelGGL(k_mfma_rate<_Float16>, dim3(blocks), dim3(4 * kWave), lds, s, out, ticks,
-                       iters);
+  switch (prec) {
+    case DMPT_SPLIT_BF16:
+      hipLaunchKernelGGL(k_mfma_rate<__bf16>, dim3(blocks), dim3(4 * kWave), lds, s, out, ticks,
+                         iters);
+      break;
+    case DMPT_SPLIT_FP16:
+      hipLaunchKernelGGL(k_mfma_rate<_Float16>, dim3(blocks), dim3(4 * kWave), lds, s, out,
+                         ticks, iters);
+      break;
+    case DMPT_FP32:
+      hipLaunchKernelGGL(k_mfma_rate_direct<float>, dim3(blocks), dim3(4 * kWave), lds, s, out,
+                         ticks, iters);
+      break;
+    case DMPT_FP64:
+      hipLaunchKernelGGL(k_mfma_rate_direct<double>, dim3(blocks), dim3(4 * kWave), lds, s, out,
+                         ticks, iters);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -134,11 +134,22 @@ std::vector<TileItem> balanced_items(const std::vector<TileItem>& items, int gri
   return out;
 }
 
-// Items of outputs 1 .. m only (no X = S^2): the adjoint products.
-std::vector<TileItem> build_items_outputs(int T, int m) {
-  std::vector<TileItem> all = build_items(T, m), v;
-  for (const TileItem& it : all)
-    if (it.out != 0) v.push_back(it);
+// Items of the adjoint products: every tile of outputs 1 .. m (one general
+// product each), bands of 8 tile rows walked column by column.
+std::vector<TileItem> build_items_all_tiles(int T, int m) {
+  std::vector<TileItem> v;
+  const int GR = 8;
+  for (int out = 1; out <= m; ++out)
+    for (int g0 = 0; g0 < T; g0 += GR)
+      for (int tj = 0; tj < T; ++tj)
+        for (int ti = g0; ti < std::min(T, g0 + GR); ++ti) {
+          TileItem it;
+          it.out = (int16_t)out;
+          it.prob = 0;
+          it.ti = ti;
+          it.tj = tj;
+          v.push_back(it);
+        }
   return v;
 }
 
@@ -373,7 +384,7 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
     get((void**)&c->st_rep, sizeof(LayerState));
     const int Ta = (int)(c->np / product_tile(c->prec == DMPT_FP64 ? DMPT_FP64 : DMPT_FP32));
     for (int k = 1; k <= 3 && k <= k_max; ++k) {
-      std::vector<TileItem> items = build_items_outputs(Ta, 1 + 2 * k);
+      std::vector<TileItem> items = build_items_all_tiles(Ta, 1 + 2 * k);
       c->adj_n_items[k] = (int)items.size();
       get((void**)&c->adj_items[k], items.size() * sizeof(TileItem));
       if (e == hipSuccess)
@@ -753,6 +764,7 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
   ba.items = c->adj_items[k];
   ba.n_items = c->adj_n_items[k];
   ba.state = nullptr;
+  ba.mode = 3;                        // one product per output on every tile
   ba.ld = ld;
   ba.kdim = np;
 
@@ -813,7 +825,7 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
         ba.x1[1 + k + j] = c->t3[j];
       }
       HIPCHK(launch_products(aprec, ba, s));
-      HIPCHK(launch_adj_update(prec, c->st, n, k, c->t2, c->sh, c->t1, c->sh1, c->t3, elems, s));
+      HIPCHK(launch_adj_update(prec, c->st, n, k, c->t2, c->sh, c->t1, c->sh1, c->t3, np, ld, s));
     }
   }
   HIPCHK(launch_adj_out(prec, c->st, c->sh, ld, dH0, c->n, s));

@@ -133,7 +133,9 @@ struct ProductArgs {
   int32_t slot_base;
   int32_t mode;              // direct forms: 0 layer products; 1 one product C = A B (A = s_hi,
                              // B = s1_hi[0], C = x) on upper tiles, mirrored (symmetric C);
-                             // 2 the same on all tiles, no mirror (general C)
+                             // 2 the same on all tiles, no mirror (general C); 3 for every
+                             // output 1 + j one product x1[j] = A_j B_j (A_j = a_op[j] or
+                             // s_hi, B_j = s1_hi[j]) on all tiles, no mirror
   const TileItem* items;
   const LayerState* state;   // NULL: compute every item, scales taken from s1_exp
   int32_t s1_exp[kMaxK];     // used when state == NULL
@@ -227,9 +229,11 @@ hipError_t launch_resplit(dmpt_precision prec, const LayerState* fwd, int j, int
                           hipStream_t s);
 hipError_t launch_adj_seed(dmpt_precision prec, const double* W, int64_t n, int64_t rows,
                            int64_t ld, void* dst, hipStream_t s);
+// One reverse layer from the one-sided products M2 = S Sh, M1_j = S Sh1_j,
+// M3_j = Sh1_j S1_j (general np x np, row stride ld; np a multiple of 32).
 hipError_t launch_adj_update(dmpt_precision prec, const LayerState* fwd, int layer, int k,
-                             const void* t2, void* sh, const void* const* t1, void* const* sh1,
-                             const void* const* t3, int64_t elems, hipStream_t s);
+                             const void* m2, void* sh, const void* const* m1, void* const* sh1,
+                             const void* const* m3, int64_t np, int64_t ld, hipStream_t s);
 hipError_t launch_adj_out(dmpt_precision prec, const LayerState* fwd, const void* src, int64_t ld,
                           double* dst, int64_t n, hipStream_t s);
 hipError_t launch_selftest_mfma(int32_t* result, hipStream_t s);

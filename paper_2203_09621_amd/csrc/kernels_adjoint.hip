@@ -123,51 +123,76 @@ struct AdjPtrs {
   const void* t3[kMaxK];
 };
 
+// One reverse layer (the adjoint of Eqs. LinTransf, S_n detailed, dB) from
+// one-sided products: for symmetric A and B, A B + B A = M + M^T with M = A B,
+// so T2 = M2 + M2^T (M2 = S Sh), T1_j = M1_j + M1_j^T (M1_j = S Sh1_j) and
+// T3_j = M3_j + M3_j^T (M3_j = Sh1_j S1_j).  With sigma = sigma_n:
+//   Sh1_j <- sigma T1_j + (1 - sigma) Sh1_j       (while S1_j was updated)
+//   Sh    <- [sigma T2 + (1 - sigma) Sh] + sum_j sigma T3_j
+// where the bracket applies while S was updated.  One 32 x 32 tile (ti, tj)
+// per block; the mirror tile of each M comes through LDS, so every global
+// access is a row of 32 consecutive elements.
 template <typename M>
 __global__ void __launch_bounds__(kBlkA) k_adj_update(const LayerState* f, int n, int k,
-                                                     const M* t2, M* sh, AdjPtrs p,
-                                                     int64_t elems) {
+                                                     const M* m2, M* sh, AdjPtrs p, int64_t ld) {
+  __shared__ M tr[32][33];
   const M sig = (M)f->sigma[n];
   const int d0l = f->d0_layer > 0 ? f->d0_layer : (1 << 30);
   const bool s_upd = n < d0l;
-  bool upd[kMaxK];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads, 4 rows each
+  // (M + M^T) at the thread's four elements (r0 + ty + 8 q, c0 + tx)
+  auto sym = [&](const M* m, M* out) {
+    __syncthreads();                           // the previous mirror tile has been read
 #pragma unroll
-  for (int j = 0; j < kMaxK; ++j) {
-    const int d1l = (j < k && f->d1_layer[j] > 0) ? f->d1_layer[j] : (1 << 30);
-    upd[j] = j < k && n < d1l;
+    for (int q = 0; q < 4; ++q) tr[ty + 8 * q][tx] = m[(c0 + ty + 8 * q) * ld + r0 + tx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = m[(r0 + ty + 8 * q) * ld + c0 + tx] + tr[tx][ty + 8 * q];
+  };
+  M v[4], t[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = sh[(r0 + ty + 8 * q) * ld + c0 + tx];
+  if (s_upd) {
+    sym(m2, t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = sig * t[q] + ((M)1 - sig) * v[q];
   }
-  for (int64_t q = (int64_t)blockIdx.x * kBlkA + threadIdx.x; q < elems;
-       q += (int64_t)gridDim.x * kBlkA) {
-    M v = sh[q];
-    if (s_upd) v = sig * t2[q] + ((M)1 - sig) * v;
+  for (int j = 0; j < k; ++j) {
+    const int d1l = f->d1_layer[j] > 0 ? f->d1_layer[j] : (1 << 30);
+    if (!(n < d1l)) continue;                  // uniform over the block
+    sym((const M*)p.t3[j], t);
 #pragma unroll
-    for (int j = 0; j < kMaxK; ++j) {
-      if (!upd[j]) continue;
-      const M* t1 = (const M*)p.t1[j];
-      const M* t3 = (const M*)p.t3[j];
-      M* s1 = (M*)p.sh1[j];
-      v += sig * t3[q];
-      s1[q] = sig * t1[q] + ((M)1 - sig) * s1[q];
+    for (int q = 0; q < 4; ++q) v[q] += sig * t[q];
+    sym((const M*)p.t1[j], t);
+    M* s1 = (M*)p.sh1[j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t at = (r0 + ty + 8 * q) * ld + c0 + tx;
+      s1[at] = sig * t[q] + ((M)1 - sig) * s1[at];
     }
-    sh[q] = v;
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sh[(r0 + ty + 8 * q) * ld + c0 + tx] = v[q];
 }
 
 hipError_t launch_adj_update(dmpt_precision prec, const LayerState* fwd, int layer, int k,
-                             const void* t2, void* sh, const void* const* t1, void* const* sh1,
-                             const void* const* t3, int64_t elems, hipStream_t s) {
+                             const void* m2, void* sh, const void* const* m1, void* const* sh1,
+                             const void* const* m3, int64_t np, int64_t ld, hipStream_t s) {
+  if (np % 32 != 0) return hipErrorInvalidValue;
   AdjPtrs p;
   for (int j = 0; j < kMaxK; ++j) {
-    p.t1[j] = j < k ? t1[j] : nullptr;
+    p.t1[j] = j < k ? m1[j] : nullptr;
     p.sh1[j] = j < k ? sh1[j] : nullptr;
-    p.t3[j] = j < k ? t3[j] : nullptr;
+    p.t3[j] = j < k ? m3[j] : nullptr;
   }
+  const dim3 grid((unsigned)(np / 32), (unsigned)(np / 32));
   if (prec == DMPT_FP64)
-    hipLaunchKernelGGL(k_adj_update<double>, dim3(4096), dim3(kBlkA), 0, s, fwd, layer, k,
-                       (const double*)t2, (double*)sh, p, elems);
+    hipLaunchKernelGGL(k_adj_update<double>, grid, dim3(kBlkA), 0, s, fwd, layer, k,
+                       (const double*)m2, (double*)sh, p, ld);
   else
-    hipLaunchKernelGGL(k_adj_update<float>, dim3(4096), dim3(kBlkA), 0, s, fwd, layer, k,
-                       (const float*)t2, (float*)sh, p, elems);
+    hipLaunchKernelGGL(k_adj_update<float>, grid, dim3(kBlkA), 0, s, fwd, layer, k,
+                       (const float*)m2, (float*)sh, p, ld);
   return hipGetLastError();
 }
 

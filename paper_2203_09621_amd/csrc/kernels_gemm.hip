@@ -591,6 +591,7 @@ k_products_direct(const ProductArgs a) {
   // the second-order chain: X2 = S1_0 S1_0 + S S2 + S2 S (S2 = s1_hi[j])
   const bool second = a.mode == 0 && it.out > 0 && a.state && j == a.state->order2_slot;
   const int nprod = (a.mode != 0 || it.out == 0) ? 1 : (second ? 3 : 2);
+  const bool each = a.mode == 3;               // one product per output, every tile
   // out 0: S S;  out 1 + j: A B + B A with A = a_op[j] (default S), B = s1_hi[j];
   // X2: S1_0 S1_0, S S2, S2 S.  Operands of product p: [A rows, B rows].
   const T *Q0[2], *Q1[2], *Q2[2];
@@ -598,7 +599,10 @@ k_products_direct(const ProductArgs a) {
     const T* s = (const T*)a.s_hi;
     const T* aa = s;
     const T* bb = s;
-    if (a.mode != 0) {
+    if (each) {
+      aa = a.a_op[j] ? (const T*)a.a_op[j] : s;   // output 1 + j: A_j B_j
+      bb = (const T*)a.s1_hi[j];
+    } else if (a.mode != 0) {
       aa = s;                                  // one product A B, A = s_hi, B = s1_hi[0]
       bb = (const T*)a.s1_hi[0];
     } else if (it.out != 0) {
@@ -700,9 +704,9 @@ k_products_direct(const ProductArgs a) {
     __syncthreads();
   }
 
-  T* C = (T*)((a.mode != 0 || it.out == 0) ? a.x : a.x1[j]);
+  T* C = (T*)(each ? a.x1[j] : ((a.mode != 0 || it.out == 0) ? a.x : a.x1[j]));
   const bool diag = it.ti == it.tj;
-  const bool mirror = a.mode != 2;
+  const bool mirror = a.mode < 2;
 #pragma unroll
   for (int m = 0; m < FM; ++m)
 #pragma unroll

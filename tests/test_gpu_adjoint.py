@@ -130,3 +130,51 @@ def test_adjoint_full_size(dm):
     print(f"adjoint N=4096: layers={st['layers']} dH0 err={e0:.2e} dH1 err={e1:.2e} "
           f"forward {st['ms']:.1f} ms adjoint {ast['ms']:.1f} ms", flush=True)
     assert e0 < TOL and e1 < TOL
+
+
+def test_adjoint_full_size_vs_fd(dm):
+    """N = 4096: the split-BF16 / FP32 adjoint against central differences
+    (h = 1e-5) of the FP64 GPU forward on 32 random entries of each gradient,
+    relative error of the sampled gradient vector within 1e-3."""
+    import torch
+    from workloads import config5
+    p = config5()
+    _, g0, g1, _, _ = _grads(dm, p, "split_bf16", 8)
+    H0, H1, W = _cuda(p.H0), _cuda(p.H1[0]), _cuda(p.W)
+    h = 1e-5
+    rng = np.random.default_rng(23)
+    pairs = [tuple(sorted(int(x) for x in rng.integers(0, p.N, 2))) for _ in range(32)]
+
+    def bump(a, i, j, d):
+        b = a.clone()
+        b[i, j] += d
+        if i != j:
+            b[j, i] += d
+        return b
+
+    def loss(P1):
+        return float((P1 * W).sum().item())
+
+    fd0, fd1 = [], []
+    ctx = dm.dmpt_init(H0, p.nocc, k_max=1, precision="fp64")
+    try:
+        for i, j in pairs:
+            fac = 1.0 if i == j else 2.0
+            lp = loss(dm.dmpt_response(ctx, [bump(H1, i, j, h)])[1][0])
+            lm = loss(dm.dmpt_response(ctx, [bump(H1, i, j, -h)])[1][0])
+            fd1.append((lp - lm) / (2 * h) / fac)
+    finally:
+        dm.dmpt_destroy(ctx)
+    for i, j in pairs:
+        fac = 1.0 if i == j else 2.0
+        lp = loss(dm.solve(bump(H0, i, j, h), [H1], p.nocc, precision="fp64")[1][0])
+        lm = loss(dm.solve(bump(H0, i, j, -h), [H1], p.nocc, precision="fp64")[1][0])
+        fd0.append((lp - lm) / (2 * h) / fac)
+    s0 = np.array([g0[i, j] for i, j in pairs])
+    s1 = np.array([g1[i, j] for i, j in pairs])
+    fd0, fd1 = np.array(fd0), np.array(fd1)
+    e0 = float(np.linalg.norm(s0 - fd0) / np.linalg.norm(fd0))
+    e1 = float(np.linalg.norm(s1 - fd1) / np.linalg.norm(fd1))
+    print(f"adjoint N=4096 vs FD on 32 entries: dH0 {e0:.2e} dH1 {e1:.2e}", flush=True)
+    assert e0 < TOL and e1 < TOL
+    del torch

@@ -560,10 +560,9 @@ template <> struct Direct<double> {
 // Same tiling with one operand copy per matrix and the 16x16x4 MFMA: a lane
 // reads one 16-byte chunk (E consecutive k) per fragment and issues E MFMAs,
 // the e-th taking element e; A and B use the same (lane group, e) -> k map.
-// WPE waves per SIMD (WPE / WGM / WGN * 4 workgroups per CU).  DMA: operands
-// go straight from global memory into LDS; else through registers, stored to
-// the other stage after the current k-tile's products.
-template <typename T, int BM, int BK, int WGM, int WGN, int SWZ, int WPE, bool DMA>
+// WPE waves per SIMD (4 WPE / (WGM WGN) workgroups per CU).  Operands go
+// straight from global memory into LDS, two stages of BK-wide k-tiles.
+template <typename T, int BM, int BK, int WGM, int WGN, int SWZ, int WPE>
 __global__ void __launch_bounds__(WGM * WGN * kWave) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_products_direct(const ProductArgs a) {
   using D = Direct<T>;
@@ -632,15 +631,14 @@ k_products_direct(const ProductArgs a) {
   const int kt_per = (int)(a.kdim / BK);
   const int ktiles = nprod * kt_per;
 
-  // DMA: in load round i, lane l of wave w writes 16-byte slot l of the
-  // wave's 1 KB block (global_load_lds_dwordx4), i.e. row i * RPL + lrow,
-  // slot lch, so it fetches the chunk whose swizzled position that slot is;
-  // the swizzle of a row does not depend on i.  Registers: the lane fetches
-  // chunk lch of its row and stores it at its swizzled slot.
-  static_assert(!DMA || ((RPL >> SWZ) % CH) == 0, "swizzle must repeat every load round");
+  // In load round i, lane l of wave w writes 16-byte slot l of the wave's
+  // 1 KB block (global_load_lds_dwordx4), i.e. row i * RPL + lrow, slot lch,
+  // so it fetches the chunk whose swizzled position that slot is; the swizzle
+  // of a row does not depend on i.
+  static_assert(((RPL >> SWZ) % CH) == 0, "swizzle must repeat every load round");
+  static_assert(kWave % CH == 0, "a wave fills whole rows");
   const int wave_u = uni(wave);
-  const int csrc = DMA ? (lch ^ ((lrow >> SWZ) & (CH - 1))) : lch;
-  u32x4 regs[DMA ? 1 : LOADS];
+  const int csrc = lch ^ ((lrow >> SWZ) & (CH - 1));
   auto issue = [&](int t) {
     const int p = t / kt_per;
     const int64_t k0 = (int64_t)(t - p * kt_per) * BK;
@@ -652,21 +650,8 @@ k_products_direct(const ProductArgs a) {
       const int64_t grow = (arr == 0 ? row_a0 : row_b0) + r;
       const T* basep = p == 0 ? Q0[arr] : (p == 1 ? Q1[arr] : Q2[arr]);
       const T* src = basep + grow * ld + k0 + csrc * E;
-      if constexpr (DMA) {
-        u32x4* dst = stage + (i * RPL + wave_u * (kWave / CH)) * CH;   // wave-uniform
-        __builtin_amdgcn_global_load_lds((const void*)src, (void*)dst, 16, 0, 0);
-      } else {
-        regs[i] = *(const u32x4*)src;
-      }
-    }
-  };
-  auto lstore = [&](int stage) {                  // register form only
-    if constexpr (!DMA) {
-#pragma unroll
-      for (int i = 0; i < LOADS; ++i) {
-        const int R = i * RPL + lrow;
-        lds[stage * STAGE + R * CH + (lch ^ ((R >> SWZ) & (CH - 1)))] = regs[i];
-      }
+      u32x4* dst = stage + (i * RPL + wave_u * (kWave / CH)) * CH;     // wave-uniform
+      __builtin_amdgcn_global_load_lds((const void*)src, (void*)dst, 16, 0, 0);
     }
   };
 
@@ -679,8 +664,7 @@ k_products_direct(const ProductArgs a) {
       for (int r = 0; r < 4; ++r) acc[m][n][r] = (T)0;
 
   issue(0);
-  lstore(0);
-  if constexpr (DMA) __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
+  __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
   __syncthreads();
   for (int t = 0; t < ktiles; ++t) {
     const int cur = t & 1;
@@ -722,11 +706,7 @@ k_products_direct(const ProductArgs a) {
         if constexpr (GRP < FM * FN) __builtin_amdgcn_sched_barrier(0);
       }
     }
-    if constexpr (DMA) {
-      __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);   // this wave's part of tile t + 1
-    } else {
-      if (t + 1 < ktiles) lstore(cur ^ 1);
-    }
+    __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);   // this wave's part of tile t + 1
     __syncthreads();
   }
 
@@ -757,11 +737,13 @@ k_products_direct(const ProductArgs a) {
 // ------------------------------------------------------------------ dispatch
 // Tile configurations (edge, k-tile, wave grid, LDS swizzle shift).
 constexpr int kSplitBM = 256, kSplitWGM = 2, kSplitWGN = 2;
-constexpr int kDirBM = 128, kDirWGM = 2, kDirWGN = 2;
-// FP32: 16-wide k-tiles (32 KB of LDS), four workgroups per CU, DMA loads;
-// FP64: 16-wide k-tiles (64 KB), two workgroups per CU, register-staged loads.
-constexpr int kDirBK32 = 16, kDirSWZ32 = 2, kDirWG32 = 4;
-constexpr int kDirBK64 = 16, kDirSWZ64 = 1, kDirWG64 = 2;
+// 128 x 128 tiles, 16-wide k-tiles, four waves per SIMD.  FP32: 4 waves of
+// 64 x 64 per workgroup (32 KB of LDS), four workgroups per CU.  FP64: 8 waves
+// of 64 x 32 (64 KB), two workgroups per CU; its 16x16x4 MFMA keeps its rate
+// only with few accumulators in turn, so a wave holds eight.
+constexpr int kDirBM = 128, kDirWGM = 2;
+constexpr int kDirBK32 = 16, kDirSWZ32 = 2, kDirWGN32 = 2, kDirWG32 = 4;
+constexpr int kDirBK64 = 16, kDirSWZ64 = 1, kDirWGN64 = 4, kDirWG64 = 2;
 
 int product_tile(dmpt_precision prec) {
   return (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16) ? kSplitBM : kDirBM;
@@ -852,15 +834,13 @@ hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_
       return launch_split<__bf16, false>(a, s);
     case DMPT_FP32: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK32 / 4) * 16;
-      return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN, kDirSWZ32,
-                                          kDirWG32, true>,
-                        kDirWGM * kDirWGN * kWave, lds, kDirWG32, a, s);
+      return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN32, kDirSWZ32, 4>,
+                        kDirWGM * kDirWGN32 * kWave, lds, kDirWG32, a, s);
     }
     case DMPT_FP64: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK64 / 2) * 16;
-      return launch_one(k_products_direct<double, kDirBM, kDirBK64, kDirWGM, kDirWGN, kDirSWZ64,
-                                          kDirWG64, false>,
-                        kDirWGM * kDirWGN * kWave, lds, kDirWG64, a, s);
+      return launch_one(k_products_direct<double, kDirBM, kDirBK64, kDirWGM, kDirWGN64, kDirSWZ64, 4>,
+                        kDirWGM * kDirWGN64 * kWave, lds, kDirWG64, a, s);
     }
   }
   return hipErrorInvalidValue;

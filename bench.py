@@ -62,6 +62,15 @@ def algorithmic_flops(n, k_active_per_layer, x_layers, precision):
     return tot
 
 
+def fp64_equivalent_flops(n, k_active_per_layer, x_layers):
+    """FLOPs of the same layers done as plain GEMMs (2 per FMA): X = S^2 as one
+    N^3 product while D0 is active, and N^3 for each active response."""
+    tot = 0.0
+    for layer, ka in enumerate(k_active_per_layer, start=1):
+        tot += 2.0 * ((n ** 3 if layer <= x_layers else 0.0) + ka * n ** 3)
+    return tot
+
+
 def k_active(stats):
     L = stats["layers"]
     ends = [d if d > 0 else L for d in stats["d1_layer"]]
@@ -423,6 +432,9 @@ def main():
                    "d1_layer": st["d1_layer"]},
         "time_to_p1_ms": round(ms, 3),
         "time_to_p1_median_ms": round(float(np.median(step_ms)), 3),
+        # the whole step's rate counting the layers' products as plain GEMMs
+        "fp64_equivalent_tflops": round(
+            fp64_equivalent_flops(p.N, k_active(st), st["x_layers"]) / (ms * 1e-3) / 1e12, 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": measured_traffic(args.workload, args.precision),

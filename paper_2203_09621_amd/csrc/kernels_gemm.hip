@@ -871,16 +871,56 @@ __global__ void __launch_bounds__(kWave) k_trace_diag(const ProblemDesc* probs,
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-#pragma unroll 4
-  for (int64_t b = 0; b < kb; ++b) {
-    const int64_t off = base + b * (kPanelRows * kPanelK);
+  // U panel blocks per batch, the next batch's loads in flight while this
+  // one's MFMAs run (the wave is alone on its SIMD: latency, not issue, is
+  // the limit); the MFMA sequence is the product's, block after block.
+  constexpr int U = 8, KS = kPanelK / 16;
+  // global-memory loads (generic ones also count as LDS traffic, so every
+  // wait on them would be a full drain)
+  typedef const __attribute__((address_space(1))) V GV;
+  V h[2][U][KS], l[2][U][KS];
+  auto fetch = [&](V (&hh)[U][KS], V (&ll)[U][KS], int64_t b0) {
 #pragma unroll
-    for (int kk = 0; kk < kPanelK / 16; ++kk) {
-      const V ah = *(const V*)(hi + off + 16 * kk);
-      const V al = *(const V*)(lo + off + 16 * kk);
-      acc = S::mma(S::up(ah), ah, acc);
-      acc = S::mma(ah, al, acc);
-      acc = S::mma(al, ah, acc);
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        const int64_t off = base + (b0 + u) * (kPanelRows * kPanelK) + 16 * kk;
+        hh[u][kk] = *(GV*)(hi + off);
+        ll[u][kk] = *(GV*)(lo + off);
+      }
+  };
+  auto mma3 = [&](const V& ah, const V& al) {
+    acc = S::mma(S::up(ah), ah, acc);
+    acc = S::mma(ah, al, acc);
+    acc = S::mma(al, ah, acc);
+  };
+  auto consume = [&](const V (&hh)[U][KS], const V (&ll)[U][KS]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) mma3(hh[u][kk], ll[u][kk]);
+  };
+  // Pairs of batches; every fetch is unconditional (a branch around one
+  // would make the wait before the next MFMAs cover it too): the last one
+  // fetches the final batch again, and nothing reads it.
+  const int64_t np2 = kb / (2 * U);
+  if (np2 > 0) fetch(h[0], l[0], 0);
+  // (scheduling fences keep each batch's loads ahead of the other's MFMAs)
+  for (int64_t q = 0; q < np2; ++q) {
+    fetch(h[1], l[1], (2 * q + 1) * U);
+    __builtin_amdgcn_sched_barrier(0);
+    consume(h[0], l[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(h[0], l[0], (q + 1 < np2 ? 2 * q + 2 : 2 * q + 1) * U);
+    __builtin_amdgcn_sched_barrier(0);
+    consume(h[1], l[1]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int64_t b = 2 * np2 * U; b < kb; ++b) {   // the remaining blocks
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const int64_t off = base + b * (kPanelRows * kPanelK) + 16 * kk;
+      mma3(*(const V*)(hi + off), *(const V*)(lo + off));
     }
   }
   // lane (c, h) holds the diagonal element of column c when h = (c / 4) % 2

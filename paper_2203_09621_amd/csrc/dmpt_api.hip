@@ -163,7 +163,7 @@ struct DevAlloc {
     return e;
   }
   void release() {
-    for (void* p : ptrs) hipFree(p);
+    for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
   }
 };
@@ -229,15 +229,15 @@ constexpr size_t kPartTotal = kPartMaxabs + kRedBlocks;
 
 void ctx_free(dmpt_ctx* c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   c->mem.release();
-  if (c->hstate) hipHostFree(c->hstate);
-  if (c->hflag) hipHostFree(c->hflag);
-  if (c->hscal) hipHostFree(c->hscal);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->hstate) (void)hipHostFree(c->hstate);
+  if (c->hflag) (void)hipHostFree(c->hflag);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (int i = 0; i < 2 * kMaxLayers; ++i)
-    if (c->pev[i]) hipEventDestroy(c->pev[i]);
+    if (c->pev[i]) (void)hipEventDestroy(c->pev[i]);
   delete c;
 }
 
@@ -614,7 +614,7 @@ dmpt_status run_response(dmpt_ctx* c, const double* const* H1, int k1, bool orde
       stats->trace_p1[j] = c->hscal[1 + j];
     }
     float ms = 0.f;
-    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) ms = 0.f;
     stats->ms = ms;
     stats->x_layers = h.d0_layer > 0 ? h.d0_layer : h.n;
     if (c->timing) {
@@ -622,7 +622,7 @@ dmpt_status run_response(dmpt_ctx* c, const double* const* H1, int k1, bool orde
       double tot = 0.0;
       for (int i = 0; i < h.n && i < n; ++i) {
         float t_ms = 0.f;
-        hipEventElapsedTime(&t_ms, c->pev[2 * i], c->pev[2 * i + 1]);
+        if (hipEventElapsedTime(&t_ms, c->pev[2 * i], c->pev[2 * i + 1]) != hipSuccess) t_ms = 0.f;
         tot += t_ms;
       }
       stats->product_ms = tot;
@@ -661,11 +661,11 @@ dmpt_status dmpt_cpscf(dmpt_ctx* c, const double* H1, dmpt_field_fn field, void*
   const size_t bytes = (size_t)n * n * sizeof(double);
   double *heff = nullptr, *prev = nullptr, *part = nullptr, *dn = nullptr;
   auto release = [&]() {
-    hipStreamSynchronize(s);
-    if (heff) hipFree(heff);
-    if (prev) hipFree(prev);
-    if (part) hipFree(part);
-    if (dn) hipFree(dn);
+    (void)hipStreamSynchronize(s);
+    if (heff) (void)hipFree(heff);
+    if (prev) (void)hipFree(prev);
+    if (part) (void)hipFree(part);
+    if (dn) (void)hipFree(dn);
   };
   if (hipMalloc((void**)&heff, bytes) != hipSuccess || hipMalloc((void**)&prev, bytes) != hipSuccess ||
       hipMalloc((void**)&part, 2 * kRedBlocks * sizeof(double)) != hipSuccess ||
@@ -840,7 +840,7 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
     stats->converged = h.converged;
     for (int j = 0; j < k; ++j) stats->d1_layer[j] = h.d1_layer[j];
     float ms = 0.f;
-    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) ms = 0.f;
     stats->ms = ms;
   }
   return DMPT_OK;
@@ -892,9 +892,9 @@ dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, c
     return fail(e == hipErrorOutOfMemory ? DMPT_ENOMEM : DMPT_EHIP, "allocation failed");
   }
   auto done = [&](dmpt_status st, const std::string& m) {
-    hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
     mem.release();
-    if (hmax) hipHostFree(hmax);
+    if (hmax) (void)hipHostFree(hmax);
     return st == DMPT_OK ? DMPT_OK : fail(st, m);
   };
   if (hipHostMalloc((void**)&hmax, sizeof(double) * kRedBlocks, 0) != hipSuccess)
@@ -961,7 +961,7 @@ dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* cons
   if (hipMalloc((void**)&part, (size_t)np * kRedBlocks * sizeof(double)) != hipSuccess)
     return fail(DMPT_ENOMEM, "allocation failed");
   if (hipMalloc((void**)&dev, (size_t)np * sizeof(double)) != hipSuccess) {
-    hipFree(part);
+    (void)hipFree(part);
     return fail(DMPT_ENOMEM, "allocation failed");
   }
   hipError_t e = hipSuccess;
@@ -972,8 +972,8 @@ dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* cons
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, dev, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(part);
-  hipFree(dev);
+  (void)hipFree(part);
+  (void)hipFree(dev);
   return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
 }
 
@@ -984,14 +984,14 @@ dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps, void* strea
   if (hipMalloc((void**)&part, 3 * 512 * sizeof(double)) != hipSuccess)
     return fail(DMPT_ENOMEM, "allocation failed");
   if (hipMalloc((void**)&dev, 2 * sizeof(double)) != hipSuccess) {
-    hipFree(part);
+    (void)hipFree(part);
     return fail(DMPT_ENOMEM, "allocation failed");
   }
   hipError_t e = launch_gershgorin(H, N, part, nullptr, dev, s);
   if (e == hipSuccess) e = hipMemcpyAsync(eps, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(part);
-  hipFree(dev);
+  (void)hipFree(part);
+  (void)hipFree(dev);
   return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
 }
 
@@ -1009,7 +1009,7 @@ dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz
   int64_t* ticks = nullptr;
   if (hipMalloc((void**)&out, (size_t)blocks * 4 * kWave * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&ticks, 2 * sizeof(int64_t)) != hipSuccess) {
-    hipFree(out);
+    (void)hipFree(out);
     return fail(DMPT_ENOMEM, "allocation failed");
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1026,10 +1026,10 @@ dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
   }
   if (e == hipSuccess) e = hipMemcpy(t, ticks, sizeof(t), hipMemcpyDeviceToHost);
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  hipFree(out);
-  hipFree(ticks);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  (void)hipFree(ticks);
   if (e != hipSuccess) return fail(DMPT_EHIP, hipGetErrorString(e));
   const double flops = (double)blocks * 4 * iters * 48 * mfma_probe_flops((dmpt_precision)precision);
   if (tflops) *tflops = ms > 0.0f ? flops / (ms * 1e-3) / 1e12 : 0.0;
@@ -1046,7 +1046,7 @@ dmpt_status dmpt_selftest_mfma(int32_t* detail, void* stream) {
   hipError_t e = launch_selftest_mfma(dev, s);
   if (e == hipSuccess) e = hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(dev);
+  (void)hipFree(dev);
   if (e != hipSuccess) return fail(DMPT_EHIP, hipGetErrorString(e));
   int32_t bad = 0;
   for (int i = 0; i < kWave; ++i) bad |= host[i];

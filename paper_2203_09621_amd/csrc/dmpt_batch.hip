@@ -325,15 +325,15 @@ hipError_t balloc(dmpt_batch* b, void** p, size_t bytes) {
 
 void batch_free(dmpt_batch* b) {
   if (!b) return;
-  if (b->stream) hipStreamSynchronize(b->stream);
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  for (void* p : b->allocs) hipFree(p);
-  if (b->host_tab) hipHostFree(b->host_tab);
-  if (b->hsum) hipHostFree(b->hsum);
-  if (b->cap) hipStreamDestroy(b->cap);
-  if (b->ev0) hipEventDestroy(b->ev0);
-  if (b->ev1) hipEventDestroy(b->ev1);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (void* p : b->allocs) (void)hipFree(p);
+  if (b->host_tab) (void)hipHostFree(b->host_tab);
+  if (b->hsum) (void)hipHostFree(b->hsum);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
   delete b;
 }
 
@@ -522,15 +522,16 @@ hipError_t autotune(dmpt_batch* b) {
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e != hipSuccess) break;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
+    e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
     b->tune_ms.push_back(ms / 3.0);
     if (ms < best) {
       best = ms;
       best_th = th;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return e;
   return build_class_items(b, best_th);
 }
@@ -714,7 +715,7 @@ dmpt_status dmpt_batch_response(dmpt_batch* b, const double* const* H0, const do
       hipGraph_t g = nullptr;
       hipError_t ee = hipStreamEndCapture(b->cap, &g);
       if (ce != hipSuccess || ee != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return bfail(DMPT_EHIP, std::string("graph capture: ") +
                                     hipGetErrorString(ce != hipSuccess ? ce : ee));
       }
@@ -729,7 +730,7 @@ dmpt_status dmpt_batch_response(dmpt_batch* b, const double* const* H0, const do
   BCHK(hipMemcpyAsync(b->hsum, b->dsum, sizeof(ProblemSummary) * P, hipMemcpyDeviceToHost, s));
   BCHK(hipStreamSynchronize(s));
   float t_ms = 0.f;
-  hipEventElapsedTime(&t_ms, b->ev0, b->ev1);
+  if (hipEventElapsedTime(&t_ms, b->ev0, b->ev1) != hipSuccess) t_ms = 0.f;
   if (ms) *ms = t_ms;
   int err = 0, noconv = 0;
   for (int p = 0; p < P; ++p) {

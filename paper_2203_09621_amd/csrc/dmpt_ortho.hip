@@ -135,7 +135,7 @@ struct ProductWork {
     return launch_products(prec, a, s);
   }
   ~ProductWork() {
-    for (void* p : allocs) hipFree(p);
+    for (void* p : allocs) (void)hipFree(p);
   }
 };
 

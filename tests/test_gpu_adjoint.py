@@ -178,3 +178,25 @@ def test_adjoint_full_size_vs_fd(dm):
     print(f"adjoint N=4096 vs FD on 32 entries: dH0 {e0:.2e} dH1 {e1:.2e}", flush=True)
     assert e0 < TOL and e1 < TOL
     del torch
+
+
+def test_adjoint_dh0_vs_mixed_second_order(dm, c5_small):
+    """<dL/dH0, E> = Tr(D2P[H1, E] W) for L = Tr(P1 W): the mixed second
+    derivative comes from two second-order responses by polarisation,
+    D2P[H1, E] = (P2(H1 + E) - P2(H1 - E)) / 2 with P2(A) the l^2 coefficient
+    for H0 + l A (FP64 GPU form), a check independent of the oracle."""
+    p = c5_small
+    _, g0, _, _, _ = _grads(dm, p, "fp64", 8)
+    rng = np.random.default_rng(29)
+    a = rng.normal(0.0, 0.01, (p.N, p.N))
+    E = np.triu(a) + np.triu(a, 1).T
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=2, precision="fp64")
+    try:
+        p2 = [dm.dmpt_response2(ctx, _cuda(p.H1[0] + s * E))[2].cpu().numpy() for s in (1.0, -1.0)]
+    finally:
+        dm.dmpt_destroy(ctx)
+    d2 = (p2[0] - p2[1]) / 2.0
+    lhs = float(np.sum(g0 * E))
+    rhs = float(np.sum(d2 * p.W))
+    print(f"<dL/dH0, E> {lhs:.10e}  Tr(D2P[H1,E] W) {rhs:.10e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)

@@ -290,6 +290,20 @@ dmpt_status dmpt_selftest_mfma(int32_t* detail, void* stream);
  * Errors: EINVAL (unknown precision), ENOMEM, EHIP. */
 dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz, void* stream);
 
+/* The dealing plan of the library's persistent product launches, on the host
+ * (no device involved).  Items of costs cost[0..n-1] keep their list order
+ * and are dealt round by round to `grid` workgroup slots (position q runs on
+ * slot q % grid) against the target max(ceil(total / grid), largest cost): a
+ * slot the next item would take past the target gets a placeholder (-1,
+ * skipped at once) and the item waits for the next slot; after a round that
+ * placed nothing the target grows by one.  order (host, capacity `cap`
+ * entries) receives, per position, the item index or -1, and *n_order the
+ * number of positions (no trailing placeholders).  When n <= grid, or the plan
+ * would need more than cap positions, the plan is the plain order 0 .. n-1.
+ * Errors: EINVAL (NULL pointers, n < 0, grid < 1, cap < n, a cost < 1). */
+dmpt_status dmpt_plan_rounds(const int64_t* cost, int32_t n, int32_t grid, int64_t cap,
+                             int32_t* order, int64_t* n_order);
+
 #ifdef __cplusplus
 }
 #endif

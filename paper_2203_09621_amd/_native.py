@@ -27,7 +27,7 @@ EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_re
            "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
            "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
-           "dmpt_selftest_mfma", "dmpt_probe_mfma"]
+           "dmpt_selftest_mfma", "dmpt_probe_mfma", "dmpt_plan_rounds"]
 
 
 class DmptOptions(ctypes.Structure):
@@ -140,6 +140,9 @@ def _load():
     lib.dmpt_selftest_mfma.restype = c_int32
     lib.dmpt_probe_mfma.argtypes = [c_int32, POINTER(c_double), POINTER(c_double), c_void_p]
     lib.dmpt_probe_mfma.restype = c_int32
+    lib.dmpt_plan_rounds.argtypes = [POINTER(c_int64), c_int32, c_int32, c_int64,
+                                     POINTER(c_int32), POINTER(c_int64)]
+    lib.dmpt_plan_rounds.restype = c_int32
     return lib
 
 
@@ -361,6 +364,23 @@ def dmpt_gershgorin(H, stream=None):
     eps = (c_double * 2)()
     _check(LIB.dmpt_gershgorin(_dev(H, "H"), H.shape[0], eps, _stream(stream)))
     return float(eps[0]), float(eps[1])
+
+
+def dmpt_plan_rounds(costs, grid: int, cap: int = None):
+    """dmpt_plan_rounds: the library's dealing plan of items with these costs
+    over `grid` slots (host only).  Returns an int32 array: per position the
+    item index or -1.  The default capacity holds any plan: every round places
+    an item or raises the target, at most (n + largest cost) rounds."""
+    import numpy as np
+    c = np.ascontiguousarray(costs, dtype=np.int64)
+    n = int(c.size)
+    if cap is None:
+        cap = (n + (int(c.max()) if n else 0) + 1) * max(int(grid), 1)
+    out = np.empty(max(cap, 1), dtype=np.int32)
+    used = c_int64(0)
+    _check(LIB.dmpt_plan_rounds(c.ctypes.data_as(POINTER(c_int64)), n, int(grid), cap,
+                                out.ctypes.data_as(POINTER(c_int32)), byref(used)))
+    return out[:used.value].copy()
 
 
 def dmpt_probe_mfma(precision: str = "split_fp16", stream=None):

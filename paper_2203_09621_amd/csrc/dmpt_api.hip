@@ -995,6 +995,19 @@ dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps, void* strea
   return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
 }
 
+dmpt_status dmpt_plan_rounds(const int64_t* cost, int32_t n, int32_t grid, int64_t cap,
+                             int32_t* order, int64_t* n_order) {
+  if (!cost || !order || !n_order || n < 0 || grid < 1 || cap < n)
+    return fail(DMPT_EINVAL, "plan_rounds: bad arguments");
+  std::vector<int64_t> c(cost, cost + n);
+  for (int64_t x : c)
+    if (x < 1) return fail(DMPT_EINVAL, "plan_rounds: costs must be >= 1");
+  const std::vector<int32_t> plan = balanced_rounds(c, grid, (size_t)cap);
+  std::copy(plan.begin(), plan.end(), order);
+  *n_order = (int64_t)plan.size();
+  return DMPT_OK;
+}
+
 dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz, void* stream) {
   if (precision < DMPT_FP64 || precision > DMPT_SPLIT_FP16)
     return fail(DMPT_EINVAL, "unknown precision");

@@ -115,8 +115,8 @@ def oracle_errors(p, P0, P1s):
 
 def cpu_baseline(p, workload, layers):
     """The FP64 oracle (eigh + sum-over-states) on the host cores, on a bounded
-    sample: the same recipe at N_s = min(N, 6144) (10-30 s on 16 host threads),
-    time scaled by (N/N_s)^3."""
+    sample: the same recipe at N_s = min(N, 8192) (about 10-20 s on 16 host
+    threads), time scaled by (N/N_s)^3."""
     from oracle import exact
     from workloads import banded_gapped_problem, dense_gapped_problem
     try:
@@ -124,7 +124,7 @@ def cpu_baseline(p, workload, layers):
         cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
-    ns = min(p.N, 6144)
+    ns = min(p.N, 8192)
     if ns == p.N:
         q = p
     elif p.basis.kind == "brickwall":

@@ -169,7 +169,8 @@ def adjoint_main(args, torch, dm):
     W = torch.from_numpy(p.W).to(dev)
     P0, P1 = torch.empty_like(H0), torch.empty_like(H0)
     g0, g1 = torch.empty_like(H0), torch.empty_like(H0)
-    ctx = dm.dmpt_init(H0, p.nocc, k_max=1, precision=prec, timing=True, ckpt_every=8)
+    ckpt = args.ckpt_every
+    ctx = dm.dmpt_init(H0, p.nocc, k_max=1, precision=prec, timing=True, ckpt_every=ckpt)
 
     def step():
         dm.dmpt_set_hamiltonian(ctx, H0)
@@ -191,8 +192,9 @@ def adjoint_main(args, torch, dm):
     layers = st["layers"]
     log(f"timed {args.steps} steps: {ms:.1f} ms/step (forward {fwd_ms:.1f}, adjoint {adj_ms:.1f})")
     # reverse layers: T2 = S Sh + Sh S, T1 = S Sh1 + Sh1 S, T3 = Sh1 S1 + S1 Sh1 in
-    # FP32, N^3 multiply-adds each (symmetric, upper tiles); the recomputation of
-    # the forward layers comes on top, so this is a lower bound on the rate
+    # FP32, each T = M + M^T from one product M on every tile (N^3 multiply-adds);
+    # the recomputation of the forward layers comes on top, so this is a lower
+    # bound on the rate
     rev = 2.0 * 3 * p.N ** 3 * layers
     achieved = rev / (adj_ms * 1e-3) / 1e12
     out = {
@@ -204,7 +206,7 @@ def adjoint_main(args, torch, dm):
         "data": "synthetic",
         "config": {"workload": p.name, "N": p.N, "nocc": p.nocc, "forward_precision": prec,
                    "adjoint_products": "f32" if prec != "fp64" else "f64",
-                   "checkpoint_every": 8, "layers": layers},
+                   "checkpoint_every": ckpt, "layers": layers},
         "forward_ms": round(fwd_ms, 3), "adjoint_ms": round(adj_ms, 3),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
                      "peak": PEAK_TFLOPS["fp32" if prec != "fp64" else "fp64"], "unit": "TFLOP/s",
@@ -357,6 +359,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=list(PEAK_TFLOPS))
     ap.add_argument("--batch-layers", type=int, default=100,
                     help="layers captured in the batched graph (c4)")
+    ap.add_argument("--ckpt-every", type=int, default=8,
+                    help="adjoint workload: checkpoint interval of the forward")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-oracle", action="store_true", help="skip the error vs the oracle")

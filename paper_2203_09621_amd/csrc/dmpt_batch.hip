@@ -55,22 +55,18 @@ struct ProblemSummary {
 constexpr int kChunkVec = 4 * kBlk;  // vectors per block-table chunk (16 K elements)
 
 // ------------------------------------------------------------------ normalisation
-// Per problem: clear the state, Gershgorin bounds of H0 (one wave per row),
-// N_S = Tr S0, and the Algorithm 1-3 scalars.
-__global__ void __launch_bounds__(kBlk) k_b_setup(BatchProblem* P, const double* const* h0tab,
-                                                 int max_layers) {
-  BatchProblem& b = P[blockIdx.x];
-  LayerState* st = b.st;
-  {
-    int32_t* w = (int32_t*)st;
-    for (size_t i = threadIdx.x; i < sizeof(LayerState) / 4; i += kBlk) w[i] = 0;
-  }
-  __syncthreads();
+// Gershgorin partials of H0 per block of 32 rows (the blocks of the Tr X
+// table): min(H_ii - r_i), max(H_ii + r_i) and sum H_ii, one wave per row.
+__global__ void __launch_bounds__(kBlk) k_b_gersh(const BatchProblem* P, const TraceBlock* T,
+                                                 const double* const* h0tab, double* part) {
+  const TraceBlock t = T[blockIdx.x];
+  const BatchProblem& b = P[t.prob];
   const double* H = h0tab[b.h0_index];
   const int64_t n = b.n;
+  const int64_t r0 = (int64_t)t.blk * 32, r1 = r0 + 32 < n ? r0 + 32 : n;
   const int lane = threadIdx.x & (kWave - 1);
   double lo = INFINITY, hi = -INFINITY, tr = 0.0;
-  for (int64_t i = threadIdx.x / kWave; i < n; i += kBlk / kWave) {
+  for (int64_t i = r0 + threadIdx.x / kWave; i < r1; i += kBlk / kWave) {
     const double* row = H + i * n;
     double r = 0.0;
     for (int64_t j = lane; j < n; j += kWave) r += (j == i) ? 0.0 : fabs(row[j]);
@@ -79,6 +75,35 @@ __global__ void __launch_bounds__(kBlk) k_b_setup(BatchProblem* P, const double*
     lo = fmin(lo, d - r);
     hi = fmax(hi, d + r);
     tr += (lane == 0) ? d : 0.0;
+  }
+  lo = block_min(lo);
+  hi = block_max(hi);
+  tr = block_sum(tr);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = lo;
+    part[3 * blockIdx.x + 1] = hi;
+    part[3 * blockIdx.x + 2] = tr;
+  }
+}
+
+// Per problem: clear the state, combine the Gershgorin partials of its row
+// blocks in a fixed order, N_S = Tr S0, and the Algorithm 1-3 scalars.
+__global__ void __launch_bounds__(kBlk) k_b_setup(BatchProblem* P, const double* gpart,
+                                                 int max_layers) {
+  BatchProblem& b = P[blockIdx.x];
+  LayerState* st = b.st;
+  {
+    int32_t* w = (int32_t*)st;
+    for (size_t i = threadIdx.x; i < sizeof(LayerState) / 4; i += kBlk) w[i] = 0;
+  }
+  __syncthreads();
+  const int64_t n = b.n;
+  double lo = INFINITY, hi = -INFINITY, tr = 0.0;
+  for (int c = threadIdx.x; c < b.tr_count; c += kBlk) {
+    const double* g = gpart + 3 * (int64_t)(b.tr_first + c);
+    lo = fmin(lo, g[0]);
+    hi = fmax(hi, g[1]);
+    tr += g[2];
   }
   lo = block_min(lo);
   hi = block_max(hi);
@@ -289,6 +314,7 @@ struct dmpt_batch {
   std::vector<TraceBlock> tb;                  // diagonal blocks of Tr X
   TraceBlock* dtb = nullptr;
   double* part_tr = nullptr;                   // per diagonal block: trace partial
+  double* part_g = nullptr;                    // per diagonal block: Gershgorin partials (3)
   double* part1m = nullptr;                    // per S1 chunk: max |H1|
   double* part_f = nullptr;                    // per tile item: fused-layer partials
   double* part_m = nullptr;
@@ -460,7 +486,9 @@ hipError_t launch_products_all(dmpt_batch* b, hipStream_t s) {
 template <typename T16>
 hipError_t enqueue_response(dmpt_batch* b, hipStream_t s) {
   const int P = b->count;
-  hipLaunchKernelGGL(k_b_setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->h0tab, b->max_layers);
+  hipLaunchKernelGGL(k_b_gersh, dim3(b->tb.size()), dim3(kBlk), 0, s, b->dp, b->dtb, b->h0tab,
+                     b->part_g);
+  hipLaunchKernelGGL(k_b_setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->part_g, b->max_layers);
   hipLaunchKernelGGL(k_b_maxabs1, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1, b->h1tab,
                      b->part1m);
   hipLaunchKernelGGL(k_b_s1setup, dim3(P), dim3(kBlk), 0, s, b->dp, b->part1m);
@@ -625,6 +653,7 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
   get((void**)&b->dc1, sizeof(Chunk) * b->c1.size());
   get((void**)&b->dtb, sizeof(TraceBlock) * b->tb.size());
   get((void**)&b->part_tr, sizeof(double) * b->tb.size());
+  get((void**)&b->part_g, sizeof(double) * 3 * b->tb.size());
   get((void**)&b->part1m, sizeof(double) * b->c1.size());
   get((void**)&b->desc, sizeof(ProblemDesc) * count);
   size_t n_big = 0, n_small = 0;

@@ -165,7 +165,10 @@ dmpt_status dmpt_cpscf(dmpt_ctx* ctx, const double* H1, dmpt_field_fn field, voi
  * checkpoints segment by segment with the recorded sigma sequence, scales
  * and stop layers (no decision is taken again); the products of the reverse
  * layers run in FP32 MFMA (FP64 for an FP64 context).  The Gershgorin bounds
- * are treated as constants.  Errors: EINVAL, EHIP. */
+ * are treated as constants.  `st` (may be NULL) receives the forward's layer
+ * counts, the time of the whole adjoint and, with timing on, product_ms /
+ * product_launches of the reverse layers' product launches.  Errors: EINVAL,
+ * EHIP. */
 dmpt_status dmpt_adjoint(dmpt_ctx* ctx, const double* const* W, int32_t k, double* dH0,
                          double* const* dH1, dmpt_stats* st);
 

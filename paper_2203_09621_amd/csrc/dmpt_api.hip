@@ -824,7 +824,9 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
         ba.s1_hi[1 + k + j] = c->seg_s1[(size_t)i * c->k_max + j];
         ba.x1[1 + k + j] = c->t3[j];
       }
+      if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1)], s));
       HIPCHK(launch_products(aprec, ba, s));
+      if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1) + 1], s));
       HIPCHK(launch_adj_update(prec, c->st, n, k, c->t2, c->sh, c->t1, c->sh1, c->t3, np, ld, s));
     }
   }
@@ -842,6 +844,17 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) ms = 0.f;
     stats->ms = ms;
+    if (c->timing) {
+      // the reverse layers' product launches, one per layer 1 .. top
+      double tot = 0.0;
+      for (int i = 0; i < top; ++i) {
+        float t_ms = 0.f;
+        if (hipEventElapsedTime(&t_ms, c->pev[2 * i], c->pev[2 * i + 1]) != hipSuccess) t_ms = 0.f;
+        tot += t_ms;
+      }
+      stats->product_ms = tot;
+      stats->product_launches = top;
+    }
   }
   return DMPT_OK;
 }

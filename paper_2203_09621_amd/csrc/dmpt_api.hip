@@ -205,7 +205,7 @@ struct dmpt_ctx {
   int ckpt;                        // checkpoint interval in layers
   int nslots;                      // checkpoint slots: layers 0, c, 2c, ...
   std::vector<void*> ck_s, ck_s1;  // [slot], [slot * k_max + j]
-  std::vector<void*> seg_s, seg_s1;// [i], [i * k_max + j], i = 0..c
+  std::vector<void*> seg_s, seg_s1;// [i], [i * k_max + j], i = 1..c (i = 0: the checkpoint)
   void* sh;                        // adjoint of S
   void* sh1[kMaxK];                // adjoints of S1_j
   void* t2;                        // S Sh + Sh S
@@ -372,8 +372,9 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
     c->seg_s1.assign((size_t)(c->ckpt + 1) * k_max, nullptr);
     for (auto& p : c->ck_s) get(&p, mat * eb);
     for (auto& p : c->ck_s1) get(&p, mat * eb);
-    for (auto& p : c->seg_s) get(&p, mat * eb);
-    for (auto& p : c->seg_s1) get(&p, mat * eb);
+    // segment store: S_{b+i}, S1_{b+i} for i = 1 .. c (i = 0 is the checkpoint)
+    for (size_t i = 1; i < c->seg_s.size(); ++i) get(&c->seg_s[i], mat * eb);
+    for (size_t i = (size_t)k_max; i < c->seg_s1.size(); ++i) get(&c->seg_s1[i], mat * eb);
     get(&c->sh, mat * eb);
     get(&c->t2, mat * eb);
     for (int j = 0; j < k_max && j < 3; ++j) {
@@ -771,48 +772,52 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
   for (int seg = top / cst; seg >= 0; --seg) {
     const int b = seg * cst, e = std::min(b + cst, top);
     if (e <= b) continue;
-    // restore S_b, S1_b and recompute S_{b+1} .. S_{e-1} with the forward's decisions
-    HIPCHK(hipMemcpyAsync(c->seg_s[0], c->ck_s[seg], mbytes, hipMemcpyDeviceToDevice, s));
-    for (int j = 0; j < k; ++j)
-      HIPCHK(hipMemcpyAsync(c->seg_s1[j], c->ck_s1[(size_t)seg * c->k_max + j], mbytes,
-                            hipMemcpyDeviceToDevice, s));
+    // S_{b+i}, S1_{b+i} (i = 0 .. e-1-b): the checkpoint for i = 0, then the
+    // segment store.  A layer that leaves S (after D0) or S1_j (after its D1
+    // layer) as it was writes nothing, and its entry points at the previous one.
+    std::vector<void*> sp(e - b), s1p((size_t)(e - b) * k);
+    sp[0] = c->ck_s[seg];
+    for (int j = 0; j < k; ++j) s1p[j] = c->ck_s1[(size_t)seg * c->k_max + j];
+    auto seg_S = [&](int i) { return sp[i]; };
+    auto seg_S1 = [&](int i, int j) { return s1p[(size_t)i * k + j]; };
+    // recompute S_{b+1} .. S_{e-1} with the forward's decisions, each layer
+    // writing its masters straight into the segment store
     if (e - 1 >= b + 1) {
-      HIPCHK(hipMemcpyAsync(c->s_master, c->seg_s[0], mbytes, hipMemcpyDeviceToDevice, s));
-      if (split)
-        HIPCHK(launch_resplit(prec, c->st, -1, 0, c->s_master, c->s_hi[0], c->s_lo[0], np, ld, t,
-                              s));
-      for (int j = 0; j < k; ++j) {
-        HIPCHK(hipMemcpyAsync(c->s1buf[j][b & 1], c->seg_s1[j], mbytes, hipMemcpyDeviceToDevice, s));
-        if (split)
-          HIPCHK(launch_resplit(prec, c->st, j, b, c->s1buf[j][b & 1], c->s1_hi[j][0],
-                                c->s1_lo[j][0], np, ld, t, s));
+      if (split) {
+        HIPCHK(launch_resplit(prec, c->st, -1, 0, seg_S(0), c->s_hi[0], c->s_lo[0], np, ld, t, s));
+        for (int j = 0; j < k; ++j)
+          HIPCHK(launch_resplit(prec, c->st, j, b, seg_S1(0, j), c->s1_hi[j][0], c->s1_lo[j][0],
+                                np, ld, t, s));
       }
       for (int n = b + 1; n <= e - 1; ++n) {
-        const int cur = n & 1, prv = cur ^ 1;
+        const int i = n - b;
+        const bool s_upd = h.d0_layer <= 0 || n < h.d0_layer;   // as the forward's flags
         HIPCHK(launch_replay_state(c->st, c->st_rep, n, s));
+        fa.s_hi = split ? c->s_hi[0] : seg_S(i - 1);
         for (int j = 0; j < k; ++j) {
-          fa.s1_hi[j] = split ? c->s1_hi[j][0] : c->s1buf[j][prv];
+          fa.s1_hi[j] = split ? c->s1_hi[j][0] : seg_S1(i - 1, j);
           fa.s1_lo[j] = c->s1_lo[j][0];
-          fa.x1[j] = c->s1buf[j][cur];
+          fa.x1[j] = c->seg_s1[(size_t)i * c->k_max + j];   // X1_j, updated in place to S1_j
         }
         HIPCHK(launch_products(prec, fa, s));
-        HIPCHK(launch_update(prec, c->st_rep, -1, c->x, c->s_master, c->s_master, c->s_hi[0],
+        HIPCHK(launch_update(prec, c->st_rep, -1, c->x, seg_S(i - 1), c->seg_s[i], c->s_hi[0],
                              c->s_lo[0], np, ld, t, c->part + kPartFro0, nullptr, s));
-        for (int j = 0; j < k; ++j)
-          HIPCHK(launch_update(prec, c->st_rep, j, c->s1buf[j][cur], c->s1buf[j][prv],
-                               c->s1buf[j][cur], c->s1_hi[j][0], c->s1_lo[j][0], np, ld, t,
+        sp[i] = s_upd ? c->seg_s[i] : sp[i - 1];
+        for (int j = 0; j < k; ++j) {
+          void* x1 = c->seg_s1[(size_t)i * c->k_max + j];
+          HIPCHK(launch_update(prec, c->st_rep, j, x1, seg_S1(i - 1, j), x1, c->s1_hi[j][0],
+                               c->s1_lo[j][0], np, ld, t,
                                c->part + kPartFro1 + (size_t)j * kRedBlocks,
                                c->part + kPartMax1 + (size_t)j * kRedBlocks, s));
-        HIPCHK(hipMemcpyAsync(c->seg_s[n - b], c->s_master, mbytes, hipMemcpyDeviceToDevice, s));
-        for (int j = 0; j < k; ++j)
-          HIPCHK(hipMemcpyAsync(c->seg_s1[(size_t)(n - b) * c->k_max + j], c->s1buf[j][cur], mbytes,
-                                hipMemcpyDeviceToDevice, s));
+          const bool s1_upd = h.d1_layer[j] <= 0 || n < h.d1_layer[j];
+          s1p[(size_t)i * k + j] = s1_upd ? x1 : s1p[(size_t)(i - 1) * k + j];
+        }
       }
     }
     // reverse layers e .. b+1
     for (int n = e; n >= b + 1; --n) {
       const int i = n - 1 - b;          // S_{n-1}, S1_{n-1} in the segment store
-      ba.s_hi = c->seg_s[i];
+      ba.s_hi = seg_S(i);
       ba.a_op[0] = nullptr;
       ba.s1_hi[0] = c->sh;
       ba.x1[0] = c->t2;
@@ -821,7 +826,7 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
         ba.s1_hi[1 + j] = c->sh1[j];
         ba.x1[1 + j] = c->t1[j];
         ba.a_op[1 + k + j] = c->sh1[j];
-        ba.s1_hi[1 + k + j] = c->seg_s1[(size_t)i * c->k_max + j];
+        ba.s1_hi[1 + k + j] = seg_S1(i, j);
         ba.x1[1 + k + j] = c->t3[j];
       }
       if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1)], s));

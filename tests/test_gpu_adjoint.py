@@ -200,3 +200,34 @@ def test_adjoint_dh0_vs_mixed_second_order(dm, c5_small):
     rhs = float(np.sum(d2 * p.W))
     print(f"<dL/dH0, E> {lhs:.10e}  Tr(D2P[H1,E] W) {rhs:.10e}", flush=True)
     assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+
+def test_two_responses(dm):
+    """k = 2, one diagonal and one dense perturbation with their own loss
+    weights: the gradients match the closed form, and checkpoint intervals 1
+    (no recomputation) and 3 give bitwise the same result."""
+    from oracle import adjoint
+    from workloads import dense_gapped_problem
+    p = dense_gapped_problem(384, 192, 0.5, 1521, h1="diag", k=1, with_w=True)
+    rng = np.random.default_rng(31)
+    a = rng.normal(0.0, 0.01, (p.N, p.N))
+    h1s = [p.H1[0], np.triu(a) + np.triu(a, 1).T]
+    b = rng.standard_normal((p.N, p.N))
+    ws = [p.W, np.triu(b) + np.triu(b, 1).T]
+
+    def run(ckpt):
+        ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=2, precision="split_bf16", ckpt_every=ckpt)
+        try:
+            _, _, st = dm.dmpt_response(ctx, [_cuda(h) for h in h1s])
+            g0, g1s, _ = dm.dmpt_adjoint(ctx, [_cuda(w) for w in ws])
+        finally:
+            dm.dmpt_destroy(ctx)
+        return st, g0.cpu().numpy(), [g.cpu().numpy() for g in g1s]
+
+    st, g0, g1s = run(3)
+    _, h0, h1g = run(1)
+    print(f"k=2: layers {st['layers']} d1 {st['d1_layer'][:2]}", flush=True)
+    assert np.array_equal(g0, h0) and all(np.array_equal(x, y) for x, y in zip(g1s, h1g))
+    r1s = adjoint.grad_h1(p.H0, ws, p.nocc)
+    r0 = adjoint.grad_h0(p.H0, h1s, ws, p.nocc)
+    assert _rel(g0, r0) < TOL and max(_rel(x, y) for x, y in zip(g1s, r1s)) < TOL

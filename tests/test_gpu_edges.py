@@ -80,16 +80,20 @@ def test_maximum_number_of_responses(dm):
 
 
 def test_full_size_configuration2(dm):
-    """N = 4096, Nocc = 2048, gap 0.5, three coordinate perturbations."""
+    """N = 4096, Nocc = 2048, gap 0.5, three coordinate perturbations, in every
+    form: FP64 within 1e-10, the split forms within 1e-3.  The plain FP32 form
+    has no stated target; it is held to 2e-3 (it reaches about 1.1e-3 here,
+    where the gap is 8e-4 of the Gershgorin width)."""
     from oracle import exact
     from workloads import config2
     p = config2()
     r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
-    for precision in ("split_fp16", "split_bf16"):
+    for precision, tol in (("fp64", FP64_TOL), ("fp32", 2e-3), ("split_fp16", SPLIT_TOL),
+                           ("split_bf16", SPLIT_TOL)):
         P0, P1s, st = _solve(dm, p.H0, p.H1, p.nocc, precision)
         e = [exact.rel_fro(P0, r0)] + [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)]
         print(f"configuration 2 {precision}: layers {st['layers']} errors {e}", flush=True)
-        assert st["converged"] and max(e) < SPLIT_TOL
+        assert st["converged"] and max(e) < tol
 
 
 def test_full_size_configuration3(dm):

@@ -19,10 +19,12 @@ Modules
                 layer is a scalar map of eigenvalues and a Hadamard scaling of
                 V^T S^(1) V (the block-function result of Mathias used in
                 Sec. IV); gives exact per-layer matrices.
-  constants  -- C_pt and the inflection points of the sigma-flip maps.
+  constants  -- C_pt, the inflection points of the sigma-flip maps, and the
+                contraction bound behind the 4.5 factor of the D0 test.
   adjoint    -- reference gradients of L = Tr(P1 W).
 
-Parity status of each function is stated in its docstring; the one unpinned
-item is the 4.5 factor of the D0 test (Algorithm 2), which the paper takes
-from earlier work without derivation: parity unpinned.
+Parity status of each function is stated in its docstring.  Every part is
+pinned; the 4.5 factor of the D0 test (Algorithm 2), which the paper takes
+from earlier work, is pinned by the exact contraction bound of a sigma-flip
+pair (constants.D0_PAIR_BOUND = 4.409 < 4.5).
 """

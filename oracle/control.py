@@ -23,7 +23,10 @@ Readings where the pseudocode is silent or garbled (listed in the design notes):
     minus k = 1), so the same C_pt applies.  It also fires on an exact zero;
     the result is S^(2)_{n-1}.
 Constants: C_pt = 9 (Sec. IV, valid on [-0.25, 1.25]); the 4.5 factor of the
-D0 test comes from earlier work (parity unpinned).
+D0 test (Alg. 2, taken from earlier work) lies just above the exact-arithmetic
+contraction bound IdErr_n <= 4.409 IdErr_{n-2}^2 of a sigma-flip pair
+(constants.D0_PAIR_BOUND), so the test fires only once rounding noise stops
+the quadratic decrease.
 """
 from __future__ import annotations
 

@@ -171,3 +171,24 @@ def test_pins_reject_mutants(mutant):
     p0 = exact.density_matrix(p.H0, p.nocc)
     idem = np.linalg.norm(p0 @ bad + bad @ p0 - bad)
     assert exact.rel_fro(fd, bad) > 1e-3 or idem > 1e-6
+
+
+def test_step_divided_differences():
+    """G_ij = theta[e_i, e_j]: the divided differences of a Fermi function so
+    steep that it is 0/1 to 1e-16 on the spectrum, and the Daleckii-Krein form
+    V (G o V^T H1 V) V^T equals the FD-pinned response of the Newton P0."""
+    p = small(seed=5)
+    e, v = exact.eigensystem(p.H0)
+    g = exact.step_divided_differences(e, p.nocc)
+    mu = 0.5 * (e[p.nocc - 1] + e[p.nocc])
+    beta = 80.0 / (e[p.nocc] - e[p.nocc - 1])
+    f = 1.0 / (1.0 + np.exp(beta * (e - mu)))
+    assert np.abs(f - (e < mu)).max() < 1e-16
+    de = e[:, None] - e[None, :]
+    off = ~np.eye(len(e), dtype=bool)
+    dd = np.zeros_like(de)
+    dd[off] = (f[:, None] - f[None, :])[off] / de[off]
+    assert np.abs(g - dd).max() < 1e-14
+    p1 = v @ (g * (v.T @ p.H1[0] @ v)) @ v.T
+    fd = exact.fd_response_2pt(p0_newton, p.H0, p.H1[0], p.nocc, 1e-4)
+    assert exact.rel_fro(p1, fd) < 1e-7

@@ -307,6 +307,17 @@ dmpt_status dmpt_probe_mfma(int32_t precision, double* tflops, double* clock_ghz
 dmpt_status dmpt_plan_rounds(const int64_t* cost, int32_t n, int32_t grid, int64_t cap,
                              int32_t* order, int64_t* n_order);
 
+/* Size of the fused layer launch of a single-problem context, on the host (no
+ * device involved): *n_positions receives the item positions (tiles plus the
+ * placeholders of the balanced rounds of dmpt_plan_rounds) of the fused
+ * split-precision launch for k responses over a T x T tile grid dealt to
+ * `grid` workgroups, and *capacity the per-item partial-sum slots a context
+ * with k_max responses allocates.  dmpt_init and dmpt_response refuse a plan
+ * longer than the capacity.  Errors: EINVAL (T < 1, k < 1, k_max < k, k_max >
+ * DMPT_MAX_K, grid < 1, NULL). */
+dmpt_status dmpt_plan_layer(int32_t T, int32_t k, int32_t k_max, int32_t grid,
+                            int64_t* n_positions, int64_t* capacity);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,4 +1,5 @@
-"""Reference gradients of L = sum_k Tr(P1_k W_k) in FP64 (test infrastructure only).
+"""Reference gradients of L = Tr(P0 W0) + sum_k Tr(P1_k W_k) in FP64 (test
+infrastructure only).
 
 P1 = DP(H0)[H1] is the first Frechet derivative of the step function
 P(H) = theta(mu I - H) (Sec. IV).  In the eigenbasis of H0 (tildes: V^T . V,
@@ -15,6 +16,10 @@ levels ascending, o = occupied, v = virtual) with D_ia = 1/(e_i - e_a):
       G~_ov =  D o (A W~_vv + B H1~_vv - H1~_oo B - W~_oo A)
   and G = V G~ V^T.
 
+* the zeroth-order term adds dTr(P0 W0)/dH0 = DP(H0)[W0] (W0 symmetrised):
+  the same self-adjoint first derivative, with W0 in place of H1.  It does not
+  reach H1.
+
 The gradient is the symmetric matrix G with dL = <G, dH> for symmetric dH
 (an off-diagonal entry perturbed together with its mirror changes L by
 2 G_ij h).  Pins: central finite differences of L computed from the exact
@@ -27,11 +32,16 @@ import numpy as np
 from .exact import check_gap, eigensystem, response_from_eigs
 
 
-def loss(h0, h1s, ws, nocc) -> float:
-    """L = sum_k Tr(P1_k W_k) from the exact P1."""
+def loss(h0, h1s, ws, nocc, w0=None) -> float:
+    """L = Tr(P0 W0) + sum_k Tr(P1_k W_k) from the exact P0 and P1 (no W0 term
+    when w0 is None)."""
     e, v = eigensystem(h0)
     check_gap(e, nocc)
-    return float(sum(np.sum(response_from_eigs(e, v, h1, nocc) * w) for h1, w in zip(h1s, ws)))
+    val = float(sum(np.sum(response_from_eigs(e, v, h1, nocc) * w) for h1, w in zip(h1s, ws)))
+    if w0 is not None:
+        vo = v[:, :nocc]
+        val += float(np.sum((vo @ vo.T) * w0))
+    return val
 
 
 def grad_h1(h0, ws, nocc):
@@ -41,8 +51,9 @@ def grad_h1(h0, ws, nocc):
     return [response_from_eigs(e, v, w, nocc) for w in ws]
 
 
-def grad_h0(h0, h1s, ws, nocc):
-    """dL/dH0 from the second-order divided differences of the step function."""
+def grad_h0(h0, h1s, ws, nocc, w0=None):
+    """dL/dH0 from the second-order divided differences of the step function,
+    plus DP(H0)[W0] for the zeroth-order term when w0 is given."""
     e, v = eigensystem(h0)
     check_gap(e, nocc)
     o = slice(0, nocc)
@@ -61,10 +72,12 @@ def grad_h0(h0, h1s, ws, nocc):
         gt[o, u] = ov
         gt[u, o] = ov.T
         g += v @ gt @ v.T
+    if w0 is not None:
+        g += response_from_eigs(e, v, 0.5 * (w0 + w0.T), nocc)
     return 0.5 * (g + g.T)
 
 
-def fd_entry(h0, h1s, ws, nocc, i, j, which: str, h: float = 1e-5) -> float:
+def fd_entry(h0, h1s, ws, nocc, i, j, which: str, h: float = 1e-5, w0=None) -> float:
     """Central difference of L for the symmetric perturbation of entry (i, j)
     (and its mirror) of H0 (which='h0') or of H1_0 (which='h1').  Returns the
     matching gradient component: dL/dh divided by 2 off the diagonal."""
@@ -73,7 +86,7 @@ def fd_entry(h0, h1s, ws, nocc, i, j, which: str, h: float = 1e-5) -> float:
     e_ij[j, i] = 1.0
     def lval(s):
         if which == "h0":
-            return loss(h0 + s * e_ij, h1s, ws, nocc)
-        return loss(h0, [h1s[0] + s * e_ij] + list(h1s[1:]), ws, nocc)
+            return loss(h0 + s * e_ij, h1s, ws, nocc, w0)
+        return loss(h0, [h1s[0] + s * e_ij] + list(h1s[1:]), ws, nocc, w0)
     dl = (lval(h) - lval(-h)) / (2.0 * h)
     return dl / (1.0 if i == j else 2.0)

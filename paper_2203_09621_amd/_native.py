@@ -27,7 +27,7 @@ EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_re
            "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
            "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
-           "dmpt_selftest_mfma", "dmpt_probe_mfma", "dmpt_plan_rounds"]
+           "dmpt_selftest_mfma", "dmpt_probe_mfma", "dmpt_plan_rounds", "dmpt_plan_layer"]
 
 
 class DmptOptions(ctypes.Structure):
@@ -143,6 +143,9 @@ def _load():
     lib.dmpt_plan_rounds.argtypes = [POINTER(c_int64), c_int32, c_int32, c_int64,
                                      POINTER(c_int32), POINTER(c_int64)]
     lib.dmpt_plan_rounds.restype = c_int32
+    lib.dmpt_plan_layer.argtypes = [c_int32, c_int32, c_int32, c_int32, POINTER(c_int64),
+                                    POINTER(c_int64)]
+    lib.dmpt_plan_layer.restype = c_int32
     return lib
 
 
@@ -383,6 +386,14 @@ def dmpt_plan_rounds(costs, grid: int, cap: int = None):
     return out[:used.value].copy()
 
 
+def dmpt_plan_layer(T: int, k: int, k_max: int, grid: int = 256):
+    """dmpt_plan_layer: (item positions of the fused launch for k responses,
+    partial-slot capacity of a context with k_max responses), host only."""
+    npos, cap = c_int64(0), c_int64(0)
+    _check(LIB.dmpt_plan_layer(int(T), int(k), int(k_max), int(grid), byref(npos), byref(cap)))
+    return npos.value, cap.value
+
+
 def dmpt_probe_mfma(precision: str = "split_fp16", stream=None):
     """dmpt_probe_mfma: (TFLOP/s, shader GHz) of back-to-back MFMAs on random operands,
     for the MFMA instruction of `precision`'s product kernels."""
@@ -455,32 +466,58 @@ def solve(H0, H1s, nocc: int, precision: str = "split_fp16", max_layers: int = 1
         dmpt_destroy(ctx)
 
 
+class _OwnedContext:
+    """A library context with its checkpoints, released exactly once: by
+    close(), or when the holder is garbage-collected (an autograd graph that is
+    dropped without a backward pass)."""
+
+    def __init__(self, ctx: c_void_p):
+        self.ctx = ctx
+
+    def close(self) -> None:
+        ctx, self.ctx = self.ctx, None
+        if ctx is not None and ctx.value:
+            dmpt_destroy(ctx)
+
+    def __del__(self):
+        self.close()
+
+
 def response_function():
     """torch.autograd.Function: P1 = DMPTResponse.apply(H0, H1, nocc, precision, ckpt_every).
     Its backward calls dmpt_adjoint; gradients follow the symmetric convention
-    (dL = <G, dH> for symmetric dH)."""
+    (dL = <G, dH> for symmetric dH).  The context (with its checkpoints) lives
+    until the backward pass, or until the graph is dropped; when no input needs
+    a gradient it is released at the end of the forward."""
     torch = _torch()
 
     class DMPTResponse(torch.autograd.Function):
         @staticmethod
         def forward(fctx, H0, H1, nocc, precision="split_bf16", ckpt_every=8):
-            ctx = dmpt_init(H0.detach().contiguous(), nocc, k_max=1, precision=precision,
-                            ckpt_every=ckpt_every)
+            grad = bool(fctx.needs_input_grad[0] or fctx.needs_input_grad[1])
+            owned = _OwnedContext(dmpt_init(H0.detach().contiguous(), nocc, k_max=1,
+                                            precision=precision,
+                                            ckpt_every=ckpt_every if grad else 0))
             try:
-                _, (P1,), _ = dmpt_response(ctx, [H1.detach().contiguous()])
+                _, (P1,), _ = dmpt_response(owned.ctx, [H1.detach().contiguous()])
             except Exception:
-                dmpt_destroy(ctx)
+                owned.close()
                 raise
-            fctx.dmpt = ctx
+            if grad:
+                fctx.dmpt = owned
+            else:
+                owned.close()
             return P1
 
         @staticmethod
         def backward(fctx, gP1):
+            owned = fctx.dmpt
+            if owned is None or owned.ctx is None:
+                raise RuntimeError("DMPTResponse: backward called twice (the context is released)")
             try:
-                dH0, (dH1,), _ = dmpt_adjoint(fctx.dmpt, [gP1.contiguous()])
+                dH0, (dH1,), _ = dmpt_adjoint(owned.ctx, [gP1.contiguous()])
             finally:
-                dmpt_destroy(fctx.dmpt)
-                fctx.dmpt = None
+                owned.close()
             return dH0, dH1, None, None, None
 
     return DMPTResponse

@@ -134,6 +134,18 @@ std::vector<TileItem> balanced_items(const std::vector<TileItem>& items, int gri
   return out;
 }
 
+// Item positions of the fused launch for k responses on `grid` workgroups,
+// and the per-item partial-slot capacity of a context sized for k_max.  The
+// plan of balanced_items keeps at most twice the item count (its limit), and
+// the item count grows with k, so 2 (1 + k_max) T (T + 1) / 2 covers every
+// k <= k_max even though placeholders make the plan length non-monotonic in k.
+int64_t fused_positions(int T, int k, int grid) {
+  return (int64_t)balanced_items(build_items(T, k), grid).size();
+}
+int64_t fused_slot_capacity(int T, int k_max) {
+  return 2 * (int64_t)(1 + k_max) * T * (T + 1) / 2;
+}
+
 // Items of the adjoint products: every tile of outputs 1 .. m (one general
 // product each), bands of 8 tile rows walked column by column.
 std::vector<TileItem> build_items_all_tiles(int T, int m) {
@@ -187,6 +199,7 @@ struct dmpt_ctx {
   ProblemDesc* desc;  // split forms: buffers of the fused layer (device)
   double* part_f;     // split forms: per-item partials of the fused layer
   double* part_m;
+  int64_t part_cap;   // entries of part_f / part_m (fused_slot_capacity)
   TraceBlock* tblocks;// split forms: diagonal blocks of Tr X
   int n_tblocks;
   double* part_tr;
@@ -260,6 +273,7 @@ dmpt_status normalise(dmpt_ctx* c, const double* H0) {
     if (r != DMPT_OK) return r;
   }
   hipStream_t s = c->stream;
+  c->last_k = 0;   // checkpoints and decisions of an earlier response no longer apply
   HIPCHK(hipMemsetAsync(c->st, 0, sizeof(LayerState), s));
   HIPCHK(launch_gershgorin(H0, c->n, c->part + kPartGersh, c->st, c->dscal, s));
   HIPCHK(launch_init_s0(c->prec, H0, c->n, c->np, c->ld, c->st, c->s_init, s));
@@ -416,8 +430,13 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
                     hipMemcpyHostToDevice);
   }
   if (split) {
-    get((void**)&c->part_f, (size_t)c->n_items[k_max] * sizeof(double));
-    get((void**)&c->part_m, (size_t)c->n_items[k_max] * sizeof(double));
+    // one slot per item position of every k <= k_max (the plan's length is
+    // not monotonic in k: placeholders of balanced rounds)
+    c->part_cap = fused_slot_capacity(T, k_max);
+    for (int k = 1; k <= k_max; ++k)
+      if (c->n_items[k] > c->part_cap) return bail(DMPT_EINVAL, "item plan exceeds slot capacity");
+    get((void**)&c->part_f, (size_t)c->part_cap * sizeof(double));
+    get((void**)&c->part_m, (size_t)c->part_cap * sizeof(double));
     get((void**)&c->desc, sizeof(ProblemDesc));
     c->n_tblocks = (int)((N + 31) / 32);
     get((void**)&c->tblocks, (size_t)c->n_tblocks * sizeof(TraceBlock));
@@ -495,6 +514,9 @@ dmpt_status run_response(dmpt_ctx* c, const double* const* H1, int k1, bool orde
   const int k = k1 + (order2 ? 1 : 0);   // response slots
   auto slot_in = [&](int j) -> const double* { return j < k1 ? H1[j] : H2; };
   auto slot_out = [&](int j) -> double* { return j < k1 ? P1[j] : P2; };
+  if (k > c->k_max) return fail(DMPT_EINVAL, "more response slots than the context holds");
+  if (is_split(c->prec) && c->n_items[k] > c->part_cap)
+    return fail(DMPT_EINVAL, "fused launch has more item positions than partial slots");
   hipStream_t s = c->stream;
   if (c->check_sym)
     for (int j = 0; j < k; ++j) {
@@ -1023,6 +1045,15 @@ dmpt_status dmpt_plan_rounds(const int64_t* cost, int32_t n, int32_t grid, int64
   const std::vector<int32_t> plan = balanced_rounds(c, grid, (size_t)cap);
   std::copy(plan.begin(), plan.end(), order);
   *n_order = (int64_t)plan.size();
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_plan_layer(int32_t T, int32_t k, int32_t k_max, int32_t grid, int64_t* n_positions,
+                            int64_t* capacity) {
+  if (T < 1 || k < 1 || k_max < k || k_max > kMaxK || grid < 1 || !n_positions || !capacity)
+    return fail(DMPT_EINVAL, "plan_layer: bad arguments");
+  *n_positions = fused_positions(T, k, grid);
+  *capacity = fused_slot_capacity(T, k_max);
   return DMPT_OK;
 }
 

@@ -88,3 +88,30 @@ def test_bad_arguments(dm, args):
     with pytest.raises(dm.DmptError) as ei:
         dm.dmpt_plan_rounds(cost, grid, cap=cap)
     assert ei.value.status == -1
+
+
+def test_partial_slots_cover_every_response_count(dm):
+    """The fused launch writes one FP64 partial per item position.  Balanced
+    rounds add placeholders, so the plan's length is not monotonic in k (e.g.
+    T = 10, k = 6 has more positions than k = 7); a context sized for k_max
+    must hold the plan of every k <= k_max.  Grid 256 (one workgroup per CU),
+    every tile count T up to 128."""
+    nonmono = 0
+    for T in range(1, 129):
+        npos = [dm.dmpt_plan_layer(T, k, 8)[0] for k in range(1, 9)]
+        nonmono += any(npos[i] > npos[i + 1] for i in range(7))
+        for k_max in range(1, 9):
+            cap = dm.dmpt_plan_layer(T, 1, k_max)[1]
+            assert max(npos[:k_max]) <= cap, (T, k_max, npos[:k_max], cap)
+    assert nonmono > 0        # the case the capacity must cover does occur
+
+
+def test_plan_layer_matches_plan_rounds(dm):
+    """dmpt_plan_layer counts the positions of dmpt_plan_rounds over the fused
+    item costs: k response outputs of T (T + 1) / 2 tiles at cost 2, then X at
+    cost 1."""
+    for T, k in ((10, 6), (17, 2), (64, 1), (33, 3)):
+        tiles = T * (T + 1) // 2
+        cost = np.array([2] * (k * tiles) + [1] * tiles, dtype=np.int64)
+        order = dm.dmpt_plan_rounds(cost, 256, cap=2 * len(cost))
+        assert dm.dmpt_plan_layer(T, k, k)[0] == len(order)

@@ -73,3 +73,49 @@ def test_mutant_wrong_sign_rejected(prob):
     bad[:p.nocc, p.nocc:] = 0
     bad[p.nocc:, :p.nocc] = 0
     assert abs(np.sum((v @ bad @ v.T) * e) - dl) > 1e-4 * max(1.0, abs(dl))
+
+
+def _p0_newton(h):
+    """theta(-H) by Newton's sign iteration (no eigensolver); the generators
+    centre the gap on zero."""
+    x = h.copy()
+    for _ in range(100):
+        xn = 0.5 * (x + np.linalg.inv(x))
+        if np.linalg.norm(xn - x) <= 1e-15 * np.linalg.norm(xn):
+            break
+        x = xn
+    return 0.5 * (np.eye(h.shape[0]) - xn)
+
+
+def test_grad_h0_of_p0_term_matches_fd_of_newton_p0(prob):
+    """d Tr(P0 W0)/dH0 = DP(H0)[W0]: central differences of Tr(P0 W0) with P0
+    from the Newton sign iteration, along random entries and a direction."""
+    p, w = prob
+    w0 = sym_normal(np.random.default_rng(11), p.N, 1.0)
+    g = adjoint.grad_h0(p.H0, [], [], p.nocc, w0=w0)
+    h = 1e-5
+    rng = np.random.default_rng(12)
+    for _ in range(6):
+        i, j = sorted(rng.integers(0, p.N, 2))
+        e = np.zeros((p.N, p.N))
+        e[i, j] = e[j, i] = 1.0
+        fd = (np.sum(_p0_newton(p.H0 + h * e) * w0)
+              - np.sum(_p0_newton(p.H0 - h * e) * w0)) / (2 * h) / (1.0 if i == j else 2.0)
+        assert abs(fd - g[i, j]) <= 1e-6 * max(1.0, abs(g).max()), (i, j, fd, g[i, j])
+
+
+def test_combined_loss_gradient(prob):
+    """L = Tr(P0 W0) + Tr(P1 W): the two terms add, and H1 sees only the second."""
+    p, w = prob
+    w0 = sym_normal(np.random.default_rng(13), p.N, 1.0)
+    g = adjoint.grad_h0(p.H0, p.H1, [w], p.nocc, w0=w0)
+    e = sym_normal(np.random.default_rng(14), p.N, 1.0)
+    h = 1e-5
+    dl = (adjoint.loss(p.H0 + h * e, p.H1, [w], p.nocc, w0)
+          - adjoint.loss(p.H0 - h * e, p.H1, [w], p.nocc, w0)) / (2 * h)
+    assert abs(np.sum(g * e) - dl) <= 1e-6 * max(1.0, abs(dl))
+    # a mutant that drops the zeroth-order term fails the same check
+    g_bad = adjoint.grad_h0(p.H0, p.H1, [w], p.nocc)
+    assert abs(np.sum(g_bad * e) - dl) > 1e-4 * max(1.0, abs(dl))
+    fd1 = adjoint.fd_entry(p.H0, p.H1, [w], p.nocc, 2, 5, "h1", h=1e-4, w0=w0)
+    assert abs(fd1 - adjoint.grad_h1(p.H0, [w], p.nocc)[0][2, 5]) <= 1e-6 * max(1.0, abs(fd1))

@@ -175,7 +175,7 @@ def adjoint_main(args, torch, dm):
     def step():
         dm.dmpt_set_hamiltonian(ctx, H0)
         st = dm.dmpt_response(ctx, [H1], P0, [P1])[2]
-        ast = dm.dmpt_adjoint(ctx, [W], g0, [g1])[2]
+        ast = dm.dmpt_adjoint(ctx, [W], dH0=g0, dH1s=[g1])[2]
         return st, ast
 
     for w in range(args.warmup):

@@ -156,21 +156,34 @@ dmpt_status dmpt_cpscf(dmpt_ctx* ctx, const double* H1, dmpt_field_fn field, voi
                        double mix, double tol, int32_t max_iter, double* P0, double* P1,
                        double* G, int32_t* iters, double* change, dmpt_stats* st);
 
-/* Reverse mode of the layer recursion for L = sum_j Tr(P1_j W_j), applied to
- * the most recent successful dmpt_response of this context (same k, k <= 3;
- * the context needs ckpt_every > 0).  W[j] (host array of device FP64 N x N)
- * is the upstream gradient dL/dP1_j; it is symmetrised.  Writes the symmetric
- * gradients dH0 = dL/dH0 and dH1[j] = dL/dH1_j (device FP64 N x N, with
- * dL = <G, dH> for symmetric dH).  The forward is recomputed from the
- * checkpoints segment by segment with the recorded sigma sequence, scales
- * and stop layers (no decision is taken again); the products of the reverse
- * layers run in FP32 MFMA (FP64 for an FP64 context).  The Gershgorin bounds
- * are treated as constants.  `st` (may be NULL) receives the forward's layer
- * counts, the time of the whole adjoint and, with timing on, product_ms /
- * product_launches of the reverse layers' product launches.  Errors: EINVAL,
- * EHIP. */
-dmpt_status dmpt_adjoint(dmpt_ctx* ctx, const double* const* W, int32_t k, double* dH0,
-                         double* const* dH1, dmpt_stats* st);
+/* Reverse mode of the layer recursion for L = Tr(P0 W0) + sum_j Tr(P1_j W_j)
+ * (the adjoint of Algorithms 1-3; P0 and P1_j are functions of H0 and H1_j,
+ * Sec. IV), applied to the most recent successful dmpt_response of this
+ * context (same k, k <= 3; the context needs ckpt_every > 0).  W[j] (host
+ * array of device FP64 N x N) is the upstream gradient dL/dP1_j and W0 (device
+ * FP64 N x N, may be NULL) dL/dP0; both are symmetrised.  Writes the
+ * symmetric gradients dH0 = dL/dH0 and dH1[j] = dL/dH1_j (device FP64 N x N,
+ * with dL = <G, dH> for symmetric dH; W0 reaches dH0 only).  The forward is
+ * recomputed from the checkpoints segment by segment with the recorded sigma
+ * sequence, scales and stop layers (no decision is taken again); the
+ * products of the reverse layers run in FP32 MFMA (FP64 for an FP64
+ * context).  The Gershgorin bounds are treated as constants.  `st` (may be
+ * NULL) receives the forward's layer counts, the time of the whole adjoint
+ * and, with timing on, product_ms / product_launches of the reverse layers'
+ * product launches.  Errors: EINVAL (no converged response since the last
+ * dmpt_init / dmpt_set_hamiltonian, k mismatch, NULL), EHIP. */
+dmpt_status dmpt_adjoint(dmpt_ctx* ctx, const double* const* W, int32_t k, const double* W0,
+                         double* dH0, double* const* dH1, dmpt_stats* st);
+
+/* Forward and reverse in one call: dmpt_response for H1[0..k-1] (P0 may be
+ * NULL, P1 as in dmpt_response), then dmpt_adjoint with W, W0 (may be NULL)
+ * into dH0, dH1.  The context needs ckpt_every > 0 and k <= 3.  `st` receives
+ * the forward's statistics with ms, product_ms and product_launches summed
+ * over both passes.  Errors: as dmpt_response and dmpt_adjoint. */
+dmpt_status dmpt_response_adjoint(dmpt_ctx* ctx, const double* const* H1, int32_t k,
+                                  const double* const* W, const double* W0, double* P0,
+                                  double* const* P1, double* dH0, double* const* dH1,
+                                  dmpt_stats* st);
 
 /* Release the context and its workspace.  NULL is allowed. */
 void dmpt_destroy(dmpt_ctx* ctx);
@@ -271,6 +284,17 @@ const char* dmpt_last_error(void);
  * layer.  Errors: EINVAL, ENOMEM, EHIP, ENOTSUP. */
 dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, const double* S1,
                                 double* X, double* X1, void* stream);
+
+/* The trace the split precisions take before the layer products (Algorithm
+ * 1's N_X = Tr X with X = S^2): part[b] (device, ceil(N/32) FP64 entries)
+ * receives the FP64 sum of X_ii over rows 32 b .. 32 b + 31, each X_ii formed
+ * from the 32 x 32 diagonal fragment alone with the operand chunks, k order
+ * and MFMA sequence of dmpt_layer_products in the same precision, so that
+ * every X_ii equals that product's diagonal bitwise.  S: device N x N FP64,
+ * split as a layer splits it.  Errors: ENOTSUP (not a split precision),
+ * EINVAL, ENOMEM, EHIP. */
+dmpt_status dmpt_layer_trace(int32_t precision, int64_t N, const double* S, double* part,
+                             void* stream);
 
 /* Gershgorin bounds (Sec. II.B) of a device N x N FP64 matrix into host eps[2]. */
 dmpt_status dmpt_gershgorin(const double* H, int64_t N, double* eps /* host, 2 */, void* stream);

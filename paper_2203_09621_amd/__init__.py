@@ -9,11 +9,12 @@ _API = ("EXPORTS", "PRECISION", "DmptError", "dmpt_adjoint", "dmpt_batch_destroy
         "dmpt_contract", "dmpt_cpscf", "dmpt_inverse_factor", "solve_nonorth",
         "dmpt_destroy",
         "dmpt_gershgorin",
-        "dmpt_init", "dmpt_layer_products", "dmpt_plan_rounds", "dmpt_plan_layer",
+        "dmpt_init", "dmpt_layer_products", "dmpt_layer_trace", "dmpt_plan_rounds", "dmpt_plan_layer",
         "dmpt_probe_mfma",
         "dmpt_response", "dmpt_response2",
         "dmpt_selftest_mfma",
-        "dmpt_set_hamiltonian", "response_function", "solve")
+        "dmpt_set_hamiltonian", "response_function", "density_function",
+        "dmpt_response_adjoint", "solve")
 
 
 def __getattr__(name):

@@ -23,11 +23,11 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
            "dmpt_response2", "dmpt_contract", "dmpt_inverse_factor", "dmpt_congruence",
-           "dmpt_cpscf",
-           "dmpt_adjoint", "dmpt_destroy", "dmpt_batch_init", "dmpt_batch_response",
-           "dmpt_batch_info", "dmpt_batch_destroy",
-           "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_gershgorin",
-           "dmpt_selftest_mfma", "dmpt_probe_mfma", "dmpt_plan_rounds", "dmpt_plan_layer"]
+           "dmpt_cpscf", "dmpt_adjoint", "dmpt_response_adjoint", "dmpt_destroy",
+           "dmpt_batch_init", "dmpt_batch_response", "dmpt_batch_info", "dmpt_batch_destroy",
+           "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_layer_trace",
+           "dmpt_gershgorin", "dmpt_selftest_mfma", "dmpt_probe_mfma", "dmpt_plan_rounds",
+           "dmpt_plan_layer"]
 
 
 class DmptOptions(ctypes.Structure):
@@ -111,9 +111,13 @@ def _load():
     lib.dmpt_inverse_factor.restype = c_int32
     lib.dmpt_congruence.argtypes = [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.dmpt_congruence.restype = c_int32
-    lib.dmpt_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p,
+    lib.dmpt_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, c_void_p, c_void_p,
                                  POINTER(c_void_p), POINTER(DmptStats)]
     lib.dmpt_adjoint.restype = c_int32
+    lib.dmpt_response_adjoint.argtypes = [c_void_p, POINTER(c_void_p), c_int32, POINTER(c_void_p),
+                                          c_void_p, c_void_p, POINTER(c_void_p), c_void_p,
+                                          POINTER(c_void_p), POINTER(DmptStats)]
+    lib.dmpt_response_adjoint.restype = c_int32
     lib.dmpt_batch_init.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_int64), POINTER(c_int64),
                                     POINTER(c_int32), POINTER(DmptOptions), c_void_p]
     lib.dmpt_batch_init.restype = c_int32
@@ -134,6 +138,8 @@ def _load():
     lib.dmpt_layer_products.argtypes = [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_void_p]
     lib.dmpt_layer_products.restype = c_int32
+    lib.dmpt_layer_trace.argtypes = [c_int32, c_int64, c_void_p, c_void_p, c_void_p]
+    lib.dmpt_layer_trace.restype = c_int32
     lib.dmpt_gershgorin.argtypes = [c_void_p, c_int64, POINTER(c_double), c_void_p]
     lib.dmpt_gershgorin.restype = c_int32
     lib.dmpt_selftest_mfma.argtypes = [POINTER(c_int32), c_void_p]
@@ -331,9 +337,9 @@ def solve_nonorth(H0, O, H1s, nocc: int, precision: str = "split_fp16",
     return P0, P1s, st
 
 
-def dmpt_adjoint(ctx: c_void_p, Ws, dH0=None, dH1s=None):
-    """dmpt_adjoint: gradients of L = sum_k Tr(P1_k W_k) for the last response.
-    Returns (dL/dH0, [dL/dH1_k], stats)."""
+def dmpt_adjoint(ctx: c_void_p, Ws, W0=None, dH0=None, dH1s=None):
+    """dmpt_adjoint: gradients of L = Tr(P0 W0) + sum_k Tr(P1_k W_k) for the
+    last response (W0 may be None).  Returns (dL/dH0, [dL/dH1_k], stats)."""
     torch = _torch()
     k = len(Ws)
     if dH0 is None:
@@ -342,9 +348,31 @@ def dmpt_adjoint(ctx: c_void_p, Ws, dH0=None, dH1s=None):
         dH1s = [torch.empty_like(w) for w in Ws]
     w_arr = (c_void_p * k)(*[_dev(w, "W").value for w in Ws])
     g_arr = (c_void_p * k)(*[_dev(g, "dH1").value for g in dH1s])
+    w0 = _dev(W0, "W0") if W0 is not None else c_void_p(None)
     st = DmptStats()
-    _check(LIB.dmpt_adjoint(ctx, w_arr, k, _dev(dH0, "dH0"), g_arr, byref(st)))
+    _check(LIB.dmpt_adjoint(ctx, w_arr, k, w0, _dev(dH0, "dH0"), g_arr, byref(st)))
     return dH0, dH1s, st.as_dict()
+
+
+def dmpt_response_adjoint(ctx: c_void_p, H1s, Ws, W0=None, P0=None, P1s=None, dH0=None,
+                          dH1s=None):
+    """dmpt_response_adjoint: forward and reverse in one call.  Returns
+    (P0, [P1_k], dL/dH0, [dL/dH1_k], stats)."""
+    torch = _torch()
+    k = len(H1s)
+    P0 = torch.empty_like(H1s[0]) if P0 is None else P0
+    P1s = [torch.empty_like(h) for h in H1s] if P1s is None else P1s
+    dH0 = torch.empty_like(H1s[0]) if dH0 is None else dH0
+    dH1s = [torch.empty_like(h) for h in H1s] if dH1s is None else dH1s
+    arr = lambda ts, nm: (c_void_p * k)(*[_dev(t, nm).value for t in ts])   # noqa: E731
+    w0 = _dev(W0, "W0") if W0 is not None else c_void_p(None)
+    st = DmptStats()
+    status = LIB.dmpt_response_adjoint(ctx, arr(H1s, "H1"), k, arr(Ws, "W"), w0, _dev(P0, "P0"),
+                                       arr(P1s, "P1"), _dev(dH0, "dH0"), arr(dH1s, "dH1"),
+                                       byref(st))
+    stats = st.as_dict()
+    _check(status, stats)
+    return P0, P1s, dH0, dH1s, stats
 
 
 def dmpt_destroy(ctx: c_void_p) -> None:
@@ -361,6 +389,18 @@ def dmpt_layer_products(S, S1=None, precision: str = "split_fp16", stream=None):
                                    _dev(X, "X"), _dev(X1, "X1") if X1 is not None else None,
                                    _stream(stream)))
     return X, X1
+
+
+def dmpt_layer_trace(S, precision: str = "split_fp16", stream=None):
+    """dmpt_layer_trace: per 32-row block, the FP64 sum of the diagonal of S^2
+    as the split layers take it before their products.  Returns a device
+    float64 tensor of ceil(N/32) entries."""
+    torch = _torch()
+    n = S.shape[0]
+    part = torch.empty((n + 31) // 32, dtype=torch.float64, device=S.device)
+    _check(LIB.dmpt_layer_trace(PRECISION[precision], n, _dev(S, "S"), c_void_p(part.data_ptr()),
+                                _stream(stream)))
+    return part
 
 
 def dmpt_gershgorin(H, stream=None):
@@ -483,12 +523,7 @@ class _OwnedContext:
         self.close()
 
 
-def response_function():
-    """torch.autograd.Function: P1 = DMPTResponse.apply(H0, H1, nocc, precision, ckpt_every).
-    Its backward calls dmpt_adjoint; gradients follow the symmetric convention
-    (dL = <G, dH> for symmetric dH).  The context (with its checkpoints) lives
-    until the backward pass, or until the graph is dropped; when no input needs
-    a gradient it is released at the end of the forward."""
+def _autograd_function(with_p0: bool):
     torch = _torch()
 
     class DMPTResponse(torch.autograd.Function):
@@ -499,7 +534,7 @@ def response_function():
                                             precision=precision,
                                             ckpt_every=ckpt_every if grad else 0))
             try:
-                _, (P1,), _ = dmpt_response(owned.ctx, [H1.detach().contiguous()])
+                P0, (P1,), _ = dmpt_response(owned.ctx, [H1.detach().contiguous()])
             except Exception:
                 owned.close()
                 raise
@@ -507,17 +542,37 @@ def response_function():
                 fctx.dmpt = owned
             else:
                 owned.close()
-            return P1
+            return (P0, P1) if with_p0 else P1
 
         @staticmethod
-        def backward(fctx, gP1):
+        def backward(fctx, *grads):
+            gP0, gP1 = grads if with_p0 else (None, grads[0])
             owned = fctx.dmpt
             if owned is None or owned.ctx is None:
                 raise RuntimeError("DMPTResponse: backward called twice (the context is released)")
+            if gP1 is None:
+                gP1 = torch.zeros_like(gP0)
             try:
-                dH0, (dH1,), _ = dmpt_adjoint(owned.ctx, [gP1.contiguous()])
+                dH0, (dH1,), _ = dmpt_adjoint(owned.ctx, [gP1.contiguous()],
+                                              W0=None if gP0 is None else gP0.contiguous())
             finally:
                 owned.close()
             return dH0, dH1, None, None, None
 
     return DMPTResponse
+
+
+def response_function():
+    """torch.autograd.Function: P1 = DMPTResponse.apply(H0, H1, nocc, precision, ckpt_every).
+    Its backward calls dmpt_adjoint; gradients follow the symmetric convention
+    (dL = <G, dH> for symmetric dH).  The context (with its checkpoints) lives
+    until the backward pass, or until the graph is dropped; when no input needs
+    a gradient it is released at the end of the forward."""
+    return _autograd_function(False)
+
+
+def density_function():
+    """torch.autograd.Function: (P0, P1) = DMPTDensity.apply(H0, H1, nocc, precision,
+    ckpt_every); the backward takes upstream gradients of both (dL/dP0 enters
+    dmpt_adjoint as W0).  Context lifetime as response_function."""
+    return _autograd_function(True)

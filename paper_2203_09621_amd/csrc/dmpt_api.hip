@@ -745,8 +745,8 @@ dmpt_status dmpt_response2(dmpt_ctx* c, const double* H1, const double* H2, doub
   return run_response(c, h1, 1, true, H2, P0, p1, P2, stats);
 }
 
-dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double* dH0,
-                         double* const* dH1, dmpt_stats* stats) {
+dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, const double* W0,
+                         double* dH0, double* const* dH1, dmpt_stats* stats) {
   if (!c) return fail(DMPT_EINVAL, "ctx is NULL");
   if (!c->ckpt) return fail(DMPT_EINVAL, "context created without checkpoints (ckpt_every = 0)");
   if (c->last_k == 0) return fail(DMPT_EINVAL, "no converged dmpt_response to differentiate");
@@ -768,7 +768,13 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
 
   HIPCHK(hipEventRecord(c->ev0, s));
   for (int j = 0; j < k; ++j) HIPCHK(launch_adj_seed(prec, W[j], c->n, np, ld, c->sh1[j], s));
-  HIPCHK(hipMemsetAsync(c->sh, 0, mbytes, s));
+  // The reverse pass starts at layer `top` >= d0 + 1, after S froze at P0 =
+  // S_{d0-1}; a loss on P0 therefore seeds Sh there, and the frozen reverse
+  // layers pass it on unchanged (plus their S1 terms) down to layer d0 - 1.
+  if (W0)
+    HIPCHK(launch_adj_seed(prec, W0, c->n, np, ld, c->sh, s));
+  else
+    HIPCHK(hipMemsetAsync(c->sh, 0, mbytes, s));
 
   ProductArgs fa;                     // forward replay (layer precision, replay state)
   memset(&fa, 0, sizeof(fa));
@@ -886,6 +892,28 @@ dmpt_status dmpt_adjoint(dmpt_ctx* c, const double* const* W, int32_t k, double*
   return DMPT_OK;
 }
 
+dmpt_status dmpt_response_adjoint(dmpt_ctx* c, const double* const* H1, int32_t k,
+                                  const double* const* W, const double* W0, double* P0,
+                                  double* const* P1, double* dH0, double* const* dH1,
+                                  dmpt_stats* stats) {
+  if (!c) return fail(DMPT_EINVAL, "ctx is NULL");
+  if (!c->ckpt) return fail(DMPT_EINVAL, "context created without checkpoints (ckpt_every = 0)");
+  if (k < 1 || k > 3 || k > c->k_max) return fail(DMPT_EINVAL, "k out of [1, min(3, k_max)]");
+  if (!W || !dH0 || !dH1) return fail(DMPT_EINVAL, "NULL argument");
+  for (int j = 0; j < k; ++j)
+    if (!W[j] || !dH1[j]) return fail(DMPT_EINVAL, "NULL W[j] or dH1[j]");
+  dmpt_status r = dmpt_response(c, H1, k, P0, P1, stats);
+  if (r != DMPT_OK) return r;
+  dmpt_stats ast;
+  r = dmpt_adjoint(c, W, k, W0, dH0, dH1, stats ? &ast : nullptr);
+  if (r == DMPT_OK && stats) {
+    stats->ms += ast.ms;
+    stats->product_ms += ast.product_ms;
+    stats->product_launches += ast.product_launches;
+  }
+  return r;
+}
+
 dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, const double* S1,
                                 double* X, double* X1, void* stream) {
   if (precision < DMPT_FP64 || precision > DMPT_SPLIT_FP16)
@@ -985,6 +1013,67 @@ dmpt_status dmpt_layer_products(int32_t precision, int64_t N, const double* S, c
     return done(DMPT_EHIP, "copy of X1 failed");
   if (hipStreamSynchronize(s) != hipSuccess) return done(DMPT_EHIP, "synchronize failed");
   return done(DMPT_OK, "");
+}
+
+dmpt_status dmpt_layer_trace(int32_t precision, int64_t N, const double* S, double* part,
+                             void* stream) {
+  if (precision != DMPT_SPLIT_FP16 && precision != DMPT_SPLIT_BF16)
+    return fail(DMPT_ENOTSUP, "the pre-product trace belongs to the split precisions");
+  if (N < 1 || !S || !part) return fail(DMPT_EINVAL, "bad arguments");
+  const dmpt_precision prec = (dmpt_precision)precision;
+  hipStream_t s = (hipStream_t)stream;
+  const int tile = product_tile(prec);
+  const int64_t np = (N + tile - 1) / tile * tile;
+  const int64_t ld = row_stride(np);
+  const int t = lo_shift(prec);
+  const int nb = (int)((N + 31) / 32);
+  DevAlloc mem;
+  void *sm = nullptr, *sh = nullptr, *sl = nullptr;
+  LayerState* st = nullptr;
+  ProblemDesc* desc = nullptr;
+  TraceBlock* blocks = nullptr;
+  double* dpart = nullptr;
+  hipError_t e = hipSuccess;
+  auto get = [&](void** p, size_t b) {
+    if (e == hipSuccess) e = mem.get(p, b);
+  };
+  get(&sm, (size_t)np * ld * sizeof(float));
+  get(&sh, (size_t)np * np * 2);
+  get(&sl, (size_t)np * np * 2);
+  get((void**)&st, sizeof(LayerState));
+  get((void**)&desc, sizeof(ProblemDesc));
+  get((void**)&blocks, (size_t)nb * sizeof(TraceBlock));
+  get((void**)&dpart, (size_t)nb * sizeof(double));
+  if (e != hipSuccess) {
+    mem.release();
+    return fail(e == hipErrorOutOfMemory ? DMPT_ENOMEM : DMPT_EHIP, "allocation failed");
+  }
+  std::vector<TraceBlock> tb(nb);
+  for (int b = 0; b < nb; ++b) tb[b] = TraceBlock{0, b};
+  ProblemDesc d;
+  memset(&d, 0, sizeof(d));
+  d.s_hi[0] = sh;
+  d.s_lo[0] = sl;
+  d.s_master = (float*)sm;
+  d.state = st;
+  d.ld = ld;
+  d.kdim = np;
+  d.pdim = np;
+  const int32_t n_real = (int32_t)N;
+  // a fresh state: D0 open, split buffer 0; only N is set
+  if (e == hipSuccess) e = hipMemsetAsync(st, 0, sizeof(LayerState), s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&st->n_real, &n_real, sizeof(n_real), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(desc, &d, sizeof(d), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(blocks, tb.data(), tb.size() * sizeof(TraceBlock), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_from_f64(prec, S, N, np, ld, 0, t, sm, sh, sl, s);
+  if (e == hipSuccess) e = launch_trace_diag(prec, desc, blocks, nb, dpart, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part, dpart, (size_t)nb * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipStreamSynchronize(s);
+  mem.release();
+  return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
 }
 
 dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* const* B, int32_t nb,

@@ -231,3 +231,161 @@ def test_two_responses(dm):
     r1s = adjoint.grad_h1(p.H0, ws, p.nocc)
     r0 = adjoint.grad_h0(p.H0, h1s, ws, p.nocc)
     assert _rel(g0, r0) < TOL and max(_rel(x, y) for x, y in zip(g1s, r1s)) < TOL
+
+
+# ------------------------------------------------------------------ loss on P0 as well
+def _w0(n, seed=41):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((n, n))
+    return np.triu(a) + np.triu(a, 1).T
+
+
+@pytest.mark.parametrize("precision,tol", [("split_bf16", TOL), ("fp64", 1e-8)])
+def test_adjoint_with_p0_term(dm, c5_small, precision, tol):
+    """L = Tr(P0 W0) + Tr(P1 W): dL/dH0 gains DP(H0)[W0], dL/dH1 is unchanged
+    (bitwise: W0 never reaches the S1 adjoints)."""
+    from oracle import adjoint
+    p = c5_small
+    w0 = _w0(p.N)
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=1, precision=precision, ckpt_every=8)
+    try:
+        dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+        g0, (g1,), _ = dm.dmpt_adjoint(ctx, [_cuda(p.W)], W0=_cuda(w0))
+        _, (g1_plain,), _ = dm.dmpt_adjoint(ctx, [_cuda(p.W)])
+    finally:
+        dm.dmpt_destroy(ctx)
+    g0, g1 = g0.cpu().numpy(), g1.cpu().numpy()
+    r0 = adjoint.grad_h0(p.H0, p.H1, [p.W], p.nocc, w0=w0)
+    r1 = adjoint.grad_h1(p.H0, [p.W], p.nocc)[0]
+    e0, e1 = _rel(g0, r0), _rel(g1, r1)
+    print(f"adjoint with P0 term {precision}: dH0 {e0:.2e} dH1 {e1:.2e}", flush=True)
+    assert e0 < tol and e1 < tol
+    assert np.array_equal(g1, g1_plain.cpu().numpy())
+
+
+def test_adjoint_p0_term_alone_vs_fd(dm, c5_small):
+    """W = 0, W0 given: dL/dH0 = DP(H0)[W0] against the closed form and against
+    central differences (h = 1e-5) of Tr(P0 W0) from the FP64 GPU forward."""
+    from oracle import adjoint
+    p = c5_small
+    w0 = _w0(p.N, 43)
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=1, precision="fp64", ckpt_every=8)
+    try:
+        dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+        g0, (g1,), _ = dm.dmpt_adjoint(ctx, [_cuda(np.zeros_like(p.W))], W0=_cuda(w0))
+    finally:
+        dm.dmpt_destroy(ctx)
+    g0 = g0.cpu().numpy()
+    assert not np.any(g1.cpu().numpy())
+    assert _rel(g0, adjoint.grad_h0(p.H0, [], [], p.nocc, w0=w0)) < 1e-8
+    rng = np.random.default_rng(47)
+    h = 1e-5
+
+    def lval(h0):
+        P0, _, _ = dm.solve(_cuda(h0), [_cuda(p.H1[0])], p.nocc, precision="fp64")
+        return float(np.sum(P0.cpu().numpy() * w0))
+
+    for _ in range(4):
+        i, j = sorted(int(x) for x in rng.integers(0, p.N, 2))
+        e = np.zeros((p.N, p.N))
+        e[i, j] = e[j, i] = 1.0
+        fd = (lval(p.H0 + h * e) - lval(p.H0 - h * e)) / (2 * h) / (1.0 if i == j else 2.0)
+        assert abs(fd - g0[i, j]) <= TOL * np.abs(g0).max(), (i, j, fd, g0[i, j])
+
+
+def test_response_adjoint_one_call(dm, c5_small):
+    """dmpt_response_adjoint = dmpt_response then dmpt_adjoint, bitwise."""
+    p = c5_small
+    w0 = _w0(p.N, 53)
+    args = ([_cuda(p.H1[0])], [_cuda(p.W)])
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=1, precision="split_fp16", ckpt_every=4)
+    try:
+        P0, (P1,), g0, (g1,), st = dm.dmpt_response_adjoint(ctx, *args, W0=_cuda(w0))
+        Q0, (Q1,), _ = dm.dmpt_response(ctx, args[0])
+        h0, (h1,), _ = dm.dmpt_adjoint(ctx, args[1], W0=_cuda(w0))
+    finally:
+        dm.dmpt_destroy(ctx)
+    assert st["converged"]
+    for a, b in ((P0, Q0), (P1, Q1), (g0, h0), (g1, h1)):
+        assert torch_equal(a, b)
+
+
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
+
+
+def test_density_function_autograd(dm, c5_small):
+    """(P0, P1) = F.apply(H0, H1): backward of L = <P0, W0> + <P1, W>."""
+    from oracle import adjoint
+    p = c5_small
+    w0 = _w0(p.N, 59)
+    F = dm.density_function()
+    h0 = _cuda(p.H0).requires_grad_(True)
+    h1 = _cuda(p.H1[0]).requires_grad_(True)
+    P0, P1 = F.apply(h0, h1, p.nocc, "split_bf16", 8)
+    ((P0 * _cuda(w0)).sum() + (P1 * _cuda(p.W)).sum()).backward()
+    r0 = adjoint.grad_h0(p.H0, p.H1, [p.W], p.nocc, w0=w0)
+    r1 = adjoint.grad_h1(p.H0, [p.W], p.nocc)[0]
+    assert _rel(h0.grad.cpu().numpy(), r0) < TOL
+    assert _rel(h1.grad.cpu().numpy(), r1) < TOL
+
+
+def test_autograd_context_released_without_backward(dm, c5_small):
+    """A forward whose graph is dropped (or that needs no gradient) gives the
+    library workspace back: device free memory returns to its level."""
+    import gc
+    import torch
+    p = c5_small
+    F = dm.response_function()
+    h0, h1 = _cuda(p.H0), _cuda(p.H1[0])
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    with torch.no_grad():
+        F.apply(h0, h1, p.nocc, "split_bf16", 8)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (8 << 20)
+    P1 = F.apply(h0.clone().requires_grad_(True), h1, p.nocc, "split_bf16", 8)
+    torch.cuda.synchronize()
+    held = torch.cuda.mem_get_info()[0]
+    assert held < free0 - (8 << 20)          # the checkpoints are held for the backward
+    del P1
+    gc.collect()
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (8 << 20)
+
+
+def test_adjoint_after_new_hamiltonian_is_refused(dm, c5_small):
+    """dmpt_set_hamiltonian invalidates the checkpoints and decisions of the
+    previous response: dmpt_adjoint must refuse until a new response ran."""
+    p = c5_small
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=1, precision="split_bf16", ckpt_every=8)
+    try:
+        dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+        dm.dmpt_set_hamiltonian(ctx, _cuda(p.H0))
+        with pytest.raises(dm.DmptError) as ei:
+            dm.dmpt_adjoint(ctx, [_cuda(p.W)])
+        assert ei.value.status == -1
+        dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+        dm.dmpt_adjoint(ctx, [_cuda(p.W)])
+    finally:
+        dm.dmpt_destroy(ctx)
+
+
+def test_adjoint_full_size_with_p0_term(dm):
+    """N = 4096 (the adjoint workload) with L = Tr(P0 W0) + Tr(P1 W)."""
+    from oracle import adjoint
+    from workloads import config5
+    p = config5()
+    w0 = _w0(p.N, 61)
+    ctx = dm.dmpt_init(_cuda(p.H0), p.nocc, k_max=1, precision="split_bf16", ckpt_every=8)
+    try:
+        _, _, g0, (g1,), st = dm.dmpt_response_adjoint(ctx, [_cuda(p.H1[0])], [_cuda(p.W)],
+                                                       W0=_cuda(w0))
+    finally:
+        dm.dmpt_destroy(ctx)
+    r0 = adjoint.grad_h0(p.H0, p.H1, [p.W], p.nocc, w0=w0)
+    r1 = adjoint.grad_h1(p.H0, [p.W], p.nocc)[0]
+    e0, e1 = _rel(g0.cpu().numpy(), r0), _rel(g1.cpu().numpy(), r1)
+    print(f"adjoint N=4096 with P0 term: dH0 {e0:.2e} dH1 {e1:.2e} ({st['ms']:.1f} ms)", flush=True)
+    assert e0 < TOL and e1 < TOL

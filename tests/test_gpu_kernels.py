@@ -94,3 +94,21 @@ def test_layer_products_deterministic(dm):
     a = dm.dmpt_layer_products(_cuda(s), _cuda(s1), "split_fp16")
     b = dm.dmpt_layer_products(_cuda(s), _cuda(s1), "split_fp16")
     assert all(bool((u == v).all()) for u, v in zip(a, b))
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("n", [300, 1000])
+def test_layer_trace_is_the_products_diagonal(dm, precision, n):
+    """The split layers take N_X = Tr X before the products, from the diagonal
+    fragments alone.  Each block sum must be the exactly rounded FP64 sum of
+    the products' own X_ii (so every X_ii agrees bitwise; a 1-ulp difference
+    in one of them changes the exact sum)."""
+    import math
+    s, _ = _normalised_pair(n, 11 + n)
+    S = _cuda(s)
+    part = dm.dmpt_layer_trace(S, precision).cpu().numpy()
+    x, _ = dm.dmpt_layer_products(S, None, precision)
+    d = np.diag(x.cpu().numpy())
+    want = np.array([math.fsum(d[b:b + 32]) for b in range(0, n, 32)])
+    assert len(part) == len(want)
+    assert np.array_equal(part, want), np.abs(part - want).max()

@@ -177,3 +177,32 @@ def test_padded_row_stride(dm, precision, monkeypatch):
     e0, e1 = _errors(p, P0, P1s)
     tol = FP64_TOL if precision == "fp64" else SPLIT_TOL
     assert st["converged"] and e0 < tol and max(e1) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "split_fp16", "split_bf16"])
+def test_reported_idempotency_residuals(dm, precision):
+    """stats idem0 = ||P0 - P0^2||_F (Alg. 2, at the D0 layer) and idem1 =
+    ||P1 - (P0 P1 + P1 P0)||_F (Alg. 3, at the D1 layer) as the layers formed
+    them.  They equal the same residuals built from the returned P0, P1 with
+    the library's layer products (the products of those layers), and they
+    differ from the oracle's FP64 invariants on the returned matrices by at
+    most the error of those products (triangle inequality)."""
+    from oracle import exact
+    from workloads import dense_gapped_problem
+    p = dense_gapped_problem(300, 150, 0.5, 3001, h1="dense", k=1, h1_std=0.01)
+    P0, P1s, st = _solve(dm, p, precision)
+    P1 = P1s[0]
+    x, x1 = dm.dmpt_layer_products(_cuda(P0), _cuda(P1), precision)
+    x, x1 = x.cpu().numpy(), x1.cpu().numpy()
+    lay0 = float(np.linalg.norm(P0 - x))
+    lay1 = float(np.linalg.norm(P1 - x1))
+    idem0, idem1 = st["idem0"], st["idem1"][0]
+    print(f"{precision}: idem0 {idem0:.3e} (products {lay0:.3e}), idem1 {idem1:.3e} "
+          f"(products {lay1:.3e})", flush=True)
+    assert abs(idem0 - lay0) <= 1e-9 * lay0 + 1e-300
+    assert abs(idem1 - lay1) <= 1e-9 * lay1 + 1e-300
+    inv = exact.invariants(p.H0, p.H1[0], P0, P1, p.nocc)
+    err0 = float(np.linalg.norm(x - P0 @ P0))
+    err1 = float(np.linalg.norm(x1 - (P0 @ P1 + P1 @ P0)))
+    assert abs(idem0 - inv["idem_p0"]) <= err0 * (1 + 1e-9) + 1e-14
+    assert abs(idem1 - inv["idem_p1"]) <= err1 * (1 + 1e-9) + 1e-14

@@ -10,7 +10,7 @@ Inputs are resident in HBM before the timed region.
 Prints ONE JSON line on stdout; progress goes to stderr.
 
   python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4] [--precision P]
-                  [--no-fp64] [--no-cpu] [--no-oracle]
+                  [--no-fp64] [--no-cpu] [--cpu-full] [--no-oracle]
 
 Workload c4 is the batched form: 512 problems of uneven size in one
 graph-captured response per step (split BF16 unless --precision says otherwise).
@@ -110,13 +110,16 @@ def oracle_errors(p, P0, P1s):
         r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
     log(f"oracle reference: {time.perf_counter() - t:.1f} s")
     obs = [float(np.sum(h * r)) for h, r in zip(p.H1, r1s)]   # Tr(H1 P1), H1 symmetric
-    return exact.rel_fro(P0, r0), [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)], obs
+    return (exact.rel_fro(P0, r0), [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)], obs,
+            (r0, r1s))
 
 
-def cpu_baseline(p, workload, layers):
-    """The FP64 oracle (eigh + sum-over-states) on the host cores, on a bounded
-    sample: the same recipe at N_s = min(N, 8192) (about 10-20 s on 16 host
-    threads), time scaled by (N/N_s)^3."""
+def cpu_baseline(p, workload, layers, full=False):
+    """The FP64 oracle (eigh + sum-over-states) on the host cores.  By default
+    on a bounded sample: the same recipe at N_s = min(N, 8192) (about 10-30 s on
+    16 host threads), its time extrapolated by (N/N_s)^3.  With ``full`` the
+    oracle runs on the workload's own H0 at its full N (minutes at N = 16384)
+    and nothing is extrapolated."""
     from oracle import exact
     from workloads import banded_gapped_problem, dense_gapped_problem
     try:
@@ -124,7 +127,7 @@ def cpu_baseline(p, workload, layers):
         cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
-    ns = min(p.N, 8192)
+    ns = p.N if full else min(p.N, 8192)
     if ns == p.N:
         q = p
     elif p.basis.kind == "brickwall":
@@ -146,14 +149,20 @@ def cpu_baseline(p, workload, layers):
     scale = (p.N / ns) ** 3
     t_full = dt * scale
     value = 5.0 * p.N ** 3 * layers / t_full / 1e12
-    return {"value": value, "unit": "TFLOP/s (paper convention, FMA = 1)", "cores": cores,
-            "kind": "oracle",
-            "sample": f"exact FP64 oracle (LAPACK eigh + sum-over-states) on the N={ns} instance "
-                      f"of the {workload} recipe: {dt:.2f} s (eigh {t_eigh:.2f} s, P0/P1 "
-                      f"formation {t_form:.2f} s), scaled by (N/{ns})^3 = {scale:.0f} to "
-                      f"{t_full:.0f} s for N={p.N}",
-            "seconds_eigh": t_eigh, "seconds_formation": t_form,
-            "seconds_full_estimate": t_full}
+    out = {"value": value, "unit": "TFLOP/s (paper convention, FMA = 1)", "cores": cores,
+           "kind": "oracle", "measured_n": ns, "extrapolated": ns != p.N,
+           "seconds_eigh": t_eigh, "seconds_formation": t_form}
+    what = (f"exact FP64 oracle (LAPACK eigh + sum-over-states) on the N={ns} instance of the "
+            f"{workload} recipe: {dt:.2f} s (eigh {t_eigh:.2f} s, P0/P1 formation "
+            f"{t_form:.2f} s)")
+    if ns != p.N:
+        out["sample"] = (what + f"; EXTRAPOLATED by (N/{ns})^3 = {scale:.0f} to {t_full:.0f} s "
+                         f"for N={p.N} (a bounded sample; `--cpu-full` measures N={p.N})")
+        out["seconds_full_estimate"] = t_full
+    else:
+        out["sample"] = what + ", measured at the workload's full size"
+        out["seconds"] = dt
+    return out
 
 
 def adjoint_main(args, torch, dm):
@@ -369,6 +378,9 @@ def main():
                     help="adjoint workload: checkpoint interval of the forward")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the CPU oracle at the workload's full N (minutes at N = 16384) "
+                         "instead of the bounded N <= 8192 sample")
     ap.add_argument("--no-oracle", action="store_true", help="skip the error vs the oracle")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -462,12 +474,14 @@ def main():
     pi = dm.dmpt_contract(H1s, P1s)
     out["observable"] = {"tr_h1_p1": [float(pi[j, j]) for j in range(len(H1s))]}
     if not args.no_oracle:
-        e0, e1, obs = oracle_errors(p, P0.cpu().numpy(), [q.cpu().numpy() for q in P1s])
+        e0, e1, obs, refs = oracle_errors(p, P0.cpu().numpy(), [q.cpu().numpy() for q in P1s])
         out["rel_fro_err"] = {"P0": e0, "P1": e1}
         out["observable"]["oracle"] = obs
         out["observable"]["rel_err"] = [abs(pi[j, j] - o) / abs(o) for j, o in enumerate(obs)]
         log(f"errors vs oracle: P0 {e0:.2e}  P1 {[f'{x:.2e}' for x in e1]}  "
             f"Tr(H1 P1) rel {out['observable']['rel_err']}")
+    else:
+        refs = None
     if not args.no_fp64 and args.precision != "fp64":
         dm.dmpt_destroy(ctx)
         ctx = None
@@ -486,11 +500,17 @@ def main():
                            "peak": PEAK_TFLOPS["fp64"],
                            "measured_ceiling": mfma_ceiling(dm, "fp64", tf64)}
         log(f"fp64 GPU form: {ms64:.1f} ms, layers {s64['layers']}, speedup {ms64 / ms:.2f}x")
+        if refs is not None:
+            from oracle import exact
+            f0 = exact.rel_fro(P0.cpu().numpy(), refs[0])
+            f1 = [exact.rel_fro(q.cpu().numpy(), r) for q, r in zip(P1s, refs[1])]
+            out["fp64_gpu"]["rel_fro_err"] = {"P0": f0, "P1": f1}
+            log(f"fp64 GPU form errors vs oracle: P0 {f0:.2e}  P1 {[f'{x:.2e}' for x in f1]}")
         dm.dmpt_destroy(c64)
     if ctx is not None:
         dm.dmpt_destroy(ctx)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, args.workload, layers)
+        out["cpu_baseline"] = cpu_baseline(p, args.workload, layers, full=args.cpu_full)
         log(f"cpu baseline: {out['cpu_baseline']['sample']}")
     print(json.dumps(out), flush=True)
 

@@ -115,3 +115,174 @@ def test_plan_layer_matches_plan_rounds(dm):
         cost = np.array([2] * (k * tiles) + [1] * tiles, dtype=np.int64)
         order = dm.dmpt_plan_rounds(cost, 256, cap=2 * len(cost))
         assert dm.dmpt_plan_layer(T, k, k)[0] == len(order)
+
+
+# ---------------------------------------------------------------------------
+# Host model of the index arithmetic of the fused split product launch
+# (256 x 256 tiles, 32-wide k-tiles, 2 x 2 waves, two LDS stages): every
+# workgroup of the persistent grid, every item it takes, and every address
+# the kernel forms, checked against the buffers the context allocates.  The
+# formulas restate the kernel's, so a change on one side that the other does
+# not follow shows here before it reaches a GPU.
+BM, BK, WGM, WGN, SWZ = 256, 32, 2, 2, 2
+NT = WGM * WGN * 64
+CH = BK // 8                      # 16-byte chunks per row of a k-tile
+ROWS = 4 * BM                     # A_hi | A_lo | B_hi | B_lo
+STAGE = ROWS * CH                 # chunks per stage
+RPW, RPL = 64 // CH, NT // CH
+LOADS = ROWS // RPL
+PANEL_ROWS, PANEL_K = 256, 32
+WTM, WTN = BM // WGM, BM // WGN
+FM, FN = WTM // 32, WTN // 32
+LDS_CHUNKS = 2 * STAGE            # dynamic LDS of the launch, in 16-byte chunks
+
+
+def xcd_remap(b, g):
+    q, r = divmod(g, 8)
+    x, i = b % 8, b // 8
+    return x * (q + 1) + i if x < r else r * (q + 1) + (x - r) * q + i
+
+
+def layer_items(T, k):
+    """(out, ti, tj) of one fused layer: responses 1..k, then X; bands of 8
+    tile rows, each walked column by column over the upper triangle."""
+    v = []
+    for out in list(range(1, k + 1)) + [0]:
+        for g0 in range(0, T, 8):
+            g1 = min(T, g0 + 8)
+            for tj in range(g0, T):
+                for ti in range(g0, min(g1, tj + 1)):
+                    v.append((out, ti, tj))
+    return v
+
+
+def _load_model():
+    """Item-independent parts of the global->LDS loads: per (round i, thread)
+    the element offset inside a 256 x 32 panel block and the LDS chunk the
+    lane writes; and the chunk each lane reads for (row R, chunk c)."""
+    tid = np.arange(NT)
+    lane, wave = tid % 64, tid // 64
+    lrow, lsl = tid // CH, tid % CH
+    csrc = lsl ^ ((lrow >> SWZ) & (CH - 1))
+    voff = lrow * PANEL_K + csrc * 8
+    local, dst, rows, chunks = [], [], [], []
+    for i in range(LOADS):
+        arr = (i * RPL) // BM
+        local.append((arr, (i * RPL - arr * BM) * PANEL_K + voff))
+        d = (i * RPL + wave * RPW) * CH + lane
+        dst.append(d)
+        # the chunk that lands in slot d: row i RPL + lrow, chunk csrc
+        rows.append(i * RPL + lrow)
+        chunks.append(csrc)
+    return local, np.concatenate(dst), np.concatenate(rows), np.concatenate(chunks)
+
+
+def test_load_and_read_addressing_is_a_consistent_permutation():
+    local, dst, rows, chunks = _load_model()
+    # one stage: every 16-byte slot written exactly once per k-tile
+    assert dst.min() == 0 and dst.max() == STAGE - 1 and len(np.unique(dst)) == STAGE
+    # slot d holds (row, chunk); the reader of (R, c) looks in slot R CH + (c ^ swz(R))
+    held = {int(d): (int(r), int(c)) for d, r, c in zip(dst, rows, chunks)}
+    for R in range(ROWS):
+        for c in range(CH):
+            slot = R * CH + (c ^ ((R >> SWZ) & (CH - 1)))
+            assert held[slot] == (R, c)
+    # panel-block offsets of one round stay inside one 256 x 32 block
+    for arr, off in local:
+        assert 0 <= arr < 4
+        assert off.min() >= 0 and off.max() + 8 <= PANEL_ROWS * PANEL_K
+    # fragment reads: lane rows of a wave's A or B fragment, hi or lo
+    lane = np.arange(64)
+    for wm in range(WGM):
+        for wn in range(WGN):
+            for g in range(2 * (FM + FN)):
+                a_side = g < 2 * FM
+                idx = g % FM if a_side else (g - 2 * FM) % FN
+                lo = (g >= FM) if a_side else (g >= 2 * FM + FN)
+                R = (wm * WTM + idx * 32 if a_side else 2 * BM + wn * WTN + idx * 32) + lane % 32
+                for kk in range(2):
+                    c = kk * 2 + lane // 32
+                    q = (R + (BM if lo else 0)) * CH + (c ^ ((R >> SWZ) & (CH - 1)))
+                    assert q.min() >= 0 and q.max() < STAGE
+
+
+def test_epilogue_staging_and_stores_in_bounds():
+    SR, PT = 32 * WGM, BM + 4
+    ITER = SR * BM // (4 * NT)
+    # parked fragments
+    lane = np.arange(64)
+    for wm in range(WGM):
+        for wn in range(WGN):
+            for r in range(16):
+                row = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)
+                col = wn * WTN + (FN - 1) * 32 + lane % 32
+                assert row.max() < SR and (row * PT + col).max() < LDS_CHUNKS * 4
+    tid = np.arange(NT)
+    for m in range(FM):
+        lrs = []
+        for g in range(ITER):
+            e = (tid + g * NT) * 4
+            tr, lc = e // BM, e % BM
+            lr = (tr >> 5) * WTM + m * 32 + (tr & 31)
+            assert tr.max() < SR and (tr * PT + lc + 3).max() < LDS_CHUNKS * 4
+            assert lr.max() < BM and lc.max() + 3 < BM and np.all(lc % 4 == 0)
+            lrs.append(lr * BM + lc)
+        # the direct block of round m covers rows m*32 + {0..31} of both wave rows, once
+        cov = np.concatenate(lrs)
+        assert len(np.unique(cov)) == len(cov) == SR * BM // 4
+        e = np.arange(BM * (SR // 4))
+        qd, lc = e % (SR // 4), e // (SR // 4)
+        tr = 4 * qd
+        lr = (tr >> 5) * WTM + m * 32 + (tr & 31)
+        assert (tr + 3).max() < SR and np.all(lr % 4 == 0) and lr.max() + 3 < BM
+
+
+@pytest.mark.parametrize("N,k,k_max", [(256, 1, 1), (300, 2, 3), (2560, 6, 7), (4608, 2, 3),
+                                       (4096, 3, 3), (16384, 1, 1), (16384, 1, 8)])
+def test_persistent_loop_model(dm, N, k, k_max):
+    """Every workgroup of the launch the context makes for N, k (k_max slots):
+    the slot remap is a bijection, the workgroups together take every item
+    position once, each real item is a valid upper-triangle tile of an
+    existing output, its partial slot lies inside the context's capacity, and
+    every operand fetch and epilogue store lies inside its buffer."""
+    Np = -(-N // BM) * BM
+    T, ld = Np // BM, Np + 128
+    items = layer_items(T, k)
+    cost = np.array([1 if o == 0 else 2 for o, _, _ in items], dtype=np.int64)
+    order = dm.dmpt_plan_rounds(cost, 256, cap=2 * len(cost))
+    n_pos, cap = dm.dmpt_plan_layer(T, k, k_max)
+    assert len(order) == n_pos <= cap
+    grid = min(n_pos, 256)
+    slots = [xcd_remap(b, grid) for b in range(grid)]
+    assert sorted(slots) == list(range(grid))
+    taken = np.zeros(n_pos, dtype=np.int64)
+    for s in slots:
+        taken[s::grid] += 1
+    assert np.all(taken == 1)
+    # real items: every tile of every output once, in the list's order
+    real = order[order >= 0]
+    assert np.array_equal(real, np.arange(len(items)))
+    kblocks = kt_per = Np // PANEL_K
+    local, _, _, _ = _load_model()
+    max_local = max(int(off.max()) for _, off in local) + 8
+    for pos, idx in enumerate(order):
+        assert pos < cap                      # part_f / part_m slot (slot_base 0)
+        if idx < 0:
+            continue
+        out, ti, tj = items[idx]
+        assert 0 <= out <= k and 0 <= ti <= tj < T
+        nprod = 1 if out == 0 else 2
+        for t in (0, nprod * kt_per - 1):
+            p = int(t >= kt_per) + int(t >= 2 * kt_per)
+            assert p < nprod
+            kofs = (t - p * kt_per) * PANEL_ROWS * PANEL_K
+            for row0 in (ti * BM, tj * BM):
+                off = (row0 // PANEL_ROWS) * kblocks * PANEL_ROWS * PANEL_K + \
+                      (row0 % PANEL_ROWS) * PANEL_K
+                assert off + kofs >= 0 and off + kofs + max_local <= Np * Np
+        # epilogue: last row/column of the tile and its mirror
+        for grow, gcol in ((ti * BM + BM - 1, tj * BM + BM - 4), (tj * BM + BM - 1, ti * BM + BM - 4)):
+            assert grow * ld + gcol + 4 <= Np * ld
+            pi = ((grow // PANEL_ROWS) * (Np // PANEL_K) + gcol // PANEL_K) * PANEL_ROWS * PANEL_K \
+                + (grow % PANEL_ROWS) * PANEL_K + gcol % PANEL_K
+            assert gcol % PANEL_K + 4 <= PANEL_K and pi + 4 <= Np * Np

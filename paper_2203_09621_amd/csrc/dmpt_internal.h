@@ -143,6 +143,10 @@ struct ProductArgs {
   int64_t kdim;              // padded size Np: rows, columns and the k extent
   int32_t n_items;
   int32_t lo_shift;          // t
+  int32_t plain_accum;       // FP32 direct form: nonzero runs one accumulator over the whole
+                             // k range instead of blocked sums (faster, less accurate; the
+                             // adjoint's reverse products, whose error the forward dominates)
+  int32_t pad1;
 };
 
 // ----------------------------------------------------------------- launchers

@@ -562,7 +562,15 @@ template <> struct Direct<double> {
 // the e-th taking element e; A and B use the same (lane group, e) -> k map.
 // WPE waves per SIMD (4 WPE / (WGM WGN) workgroups per CU).  Operands go
 // straight from global memory into LDS, two stages of BK-wide k-tiles.
-template <typename T, int BM, int BK, int WGM, int WGN, int SWZ, int WPE>
+//
+// FLUSH > 0: blocked accumulation.  The FP32 16x16x4 MFMA adds its four
+// products one at a time, each rounded to FP32 and then added with one more
+// rounding, so one accumulator running over the whole k range takes 2 kdim
+// roundings at the size of the full sum.  With FLUSH, the MFMAs accumulate
+// FLUSH k-tiles from zero, and that partial sum is added to a second
+// accumulator (one FP32 addition) before the next chunk starts: the error of
+// a long sum then grows with FLUSH BK + kdim / (FLUSH BK) instead of kdim.
+template <typename T, int BM, int BK, int WGM, int WGN, int SWZ, int WPE, int FLUSH = 0>
 __global__ void __launch_bounds__(WGM * WGN * kWave) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_products_direct(const ProductArgs a) {
   using D = Direct<T>;
@@ -655,13 +663,33 @@ k_products_direct(const ProductArgs a) {
     }
   };
 
-  Acc acc[FM][FN];
+  Acc acc[FM][FN], tot[FLUSH > 0 ? FM : 1][FLUSH > 0 ? FN : 1];
 #pragma unroll
   for (int m = 0; m < FM; ++m)
 #pragma unroll
     for (int n = 0; n < FN; ++n)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[m][n][r] = (T)0;
+  if constexpr (FLUSH > 0) {
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+      for (int n = 0; n < FN; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[m][n][r] = (T)0;
+  }
+  // chunk sum into the running total (FLUSH > 0 only)
+  auto flush = [&]() {
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+      for (int n = 0; n < FN; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          tot[m][n][r] += acc[m][n][r];
+          acc[m][n][r] = (T)0;
+        }
+  };
 
   issue(0);
   __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
@@ -706,8 +734,17 @@ k_products_direct(const ProductArgs a) {
         if constexpr (GRP < FM * FN) __builtin_amdgcn_sched_barrier(0);
       }
     }
+    if constexpr (FLUSH > 0) {
+      if ((t + 1) % FLUSH == 0 || t + 1 == ktiles) flush();
+    }
     __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);   // this wave's part of tile t + 1
     __syncthreads();
+  }
+  if constexpr (FLUSH > 0) {
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+      for (int n = 0; n < FN; ++n) acc[m][n] = tot[m][n];
   }
 
   T* C = (T*)(each ? a.x1[j] : ((a.mode != 0 || it.out == 0) ? a.x : a.x1[j]));
@@ -737,13 +774,18 @@ k_products_direct(const ProductArgs a) {
 // ------------------------------------------------------------------ dispatch
 // Tile configurations (edge, k-tile, wave grid, LDS swizzle shift).
 constexpr int kSplitBM = 256, kSplitWGM = 2, kSplitWGN = 2;
-// 128 x 128 tiles, 16-wide k-tiles, four waves per SIMD.  FP32: 4 waves of
-// 64 x 64 per workgroup (32 KB of LDS), four workgroups per CU.  FP64: 8 waves
-// of 64 x 32 (64 KB), two workgroups per CU; its 16x16x4 MFMA keeps its rate
+// 128 x 128 tiles, 16-wide k-tiles.  FP32: 4 waves of 64 x 64 per workgroup
+// (32 KB of LDS); with the blocked accumulation (a second set of 64
+// accumulators, 194 registers) two waves per SIMD and two workgroups per CU,
+// without it four and four.  FP64: 8 waves of 64 x 32 (64 KB), two
+// workgroups per CU, four waves per SIMD; its 16x16x4 MFMA keeps its rate
 // only with few accumulators in turn, so a wave holds eight.
 constexpr int kDirBM = 128, kDirWGM = 2;
 constexpr int kDirBK32 = 16, kDirSWZ32 = 2, kDirWGN32 = 2, kDirWG32 = 4;
 constexpr int kDirBK64 = 16, kDirSWZ64 = 1, kDirWGN64 = 4, kDirWG64 = 2;
+// FP32: the MFMAs accumulate 4 k-tiles (64 k) before the partial sum joins the
+// running total; the second set of accumulators takes two waves per SIMD.
+constexpr int kDirFlush32 = 4;
 
 int product_tile(dmpt_precision prec) {
   return (prec == DMPT_SPLIT_FP16 || prec == DMPT_SPLIT_BF16) ? kSplitBM : kDirBM;
@@ -834,8 +876,12 @@ hipError_t launch_products(dmpt_precision prec, const ProductArgs& a, hipStream_
       return launch_split<__bf16, false>(a, s);
     case DMPT_FP32: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK32 / 4) * 16;
-      return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN32, kDirSWZ32, 4>,
-                        kDirWGM * kDirWGN32 * kWave, lds, kDirWG32, a, s);
+      if (a.plain_accum)
+        return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN32, kDirSWZ32, 4>,
+                          kDirWGM * kDirWGN32 * kWave, lds, kDirWG32, a, s);
+      return launch_one(k_products_direct<float, kDirBM, kDirBK32, kDirWGM, kDirWGN32, kDirSWZ32,
+                                          2, kDirFlush32>,
+                        kDirWGM * kDirWGN32 * kWave, lds, kDirWG32 / 2, a, s);
     }
     case DMPT_FP64: {
       constexpr size_t lds = 2 * (2 * kDirBM) * (kDirBK64 / 2) * 16;

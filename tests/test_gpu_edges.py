@@ -81,14 +81,15 @@ def test_maximum_number_of_responses(dm):
 
 def test_full_size_configuration2(dm):
     """N = 4096, Nocc = 2048, gap 0.5, three coordinate perturbations, in every
-    form: FP64 within 1e-10, the split forms within 1e-3.  The plain FP32 form
-    has no stated target; it is held to 2e-3 (it reaches about 1.1e-3 here,
-    where the gap is 8e-4 of the Gershgorin width)."""
+    form: FP64 within 1e-10, the split forms and the FP32 form within 1e-3.
+    The gap is 8e-4 of the Gershgorin width here, so early product errors in
+    the occupied-virtual block are amplified; the FP32 form reaches 3.5e-5
+    with its blocked accumulation (1.1e-3 with one accumulator over k)."""
     from oracle import exact
     from workloads import config2
     p = config2()
     r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
-    for precision, tol in (("fp64", FP64_TOL), ("fp32", 2e-3), ("split_fp16", SPLIT_TOL),
+    for precision, tol in (("fp64", FP64_TOL), ("fp32", SPLIT_TOL), ("split_fp16", SPLIT_TOL),
                            ("split_bf16", SPLIT_TOL)):
         P0, P1s, st = _solve(dm, p.H0, p.H1, p.nocc, precision)
         e = [exact.rel_fro(P0, r0)] + [exact.rel_fro(a, b) for a, b in zip(P1s, r1s)]

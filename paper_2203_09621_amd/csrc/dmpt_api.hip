@@ -461,7 +461,7 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
       d.s_master = (float*)c->s_master;
       d.state = c->st;
       d.ld = c->ld;
-      d.kdim = c->np;
+      d.kdim = (N + kPanelK - 1) / kPanelK * kPanelK;
       d.pdim = c->np;
       e = hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice);
     }

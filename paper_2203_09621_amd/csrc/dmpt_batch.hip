@@ -450,8 +450,9 @@ hipError_t build_class_items(dmpt_batch* b, int threshold) {
     q.s_master = bp.s_master;
     q.state = bp.st;
     q.ld = bp.ld;
-    const int tile = which[p] ? 128 : 256;
-    q.kdim = (bp.n + tile - 1) / tile * tile;
+    // the k loop runs over N rounded up to one k-tile: the padding rows and
+    // columns are zero, so a longer k range would only add exact zeros
+    q.kdim = (bp.n + kPanelK - 1) / kPanelK * kPanelK;
     q.pdim = bp.np;
   }
   e = hipMemcpy(b->desc, d.data(), b->count * sizeof(ProblemDesc), hipMemcpyHostToDevice);

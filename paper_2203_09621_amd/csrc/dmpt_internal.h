@@ -112,7 +112,8 @@ struct ProblemDesc {
   float* s1m[kMaxK][2];      // S1_j masters
   LayerState* state;
   int64_t ld;                // row stride of the masters
-  int64_t kdim;              // k extent of the products (multiple of the tile)
+  int64_t kdim;              // k extent of the products: N rounded up to kPanelK (the
+                             // operands are zero beyond N, so every k past N adds exact zeros)
   int64_t pdim;              // panel-layout size of the 16-bit operands (multiple of 256)
 };
 

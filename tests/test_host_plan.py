@@ -262,7 +262,9 @@ def test_persistent_loop_model(dm, N, k, k_max):
     # real items: every tile of every output once, in the list's order
     real = order[order >= 0]
     assert np.array_equal(real, np.arange(len(items)))
-    kblocks = kt_per = Np // PANEL_K
+    kblocks = Np // PANEL_K                   # panel blocks per row panel (pdim)
+    kt_per = -(-N // PANEL_K)                 # k-tiles of one product (kdim = N rounded to 32)
+    assert kt_per <= kblocks
     local, _, _, _ = _load_model()
     max_local = max(int(off.max()) for _, off in local) + 8
     for pos, idx in enumerate(order):

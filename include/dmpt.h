@@ -247,6 +247,19 @@ void dmpt_batch_destroy(dmpt_batch* batch);
 dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* const* B, int32_t nb,
                           int64_t N, double* out, void* stream);
 
+/* dmpt_contract without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and reduction order as
+ * dmpt_contract (the results are bitwise the same), with its partial sums in a
+ * fixed device array of the library (520 KiB per GPU, held until the process
+ * ends) instead of per-call buffers.  At most 64 pairs: na * nb > 64 returns
+ * EINVAL.  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (several streams or threads at once) race and give undefined
+ * results.  Errors: EINVAL (NULL or misaligned pointer, na or nb < 1, na * nb
+ * > 64), EHIP. */
+dmpt_status dmpt_contract_noalloc(const double* const* A, int32_t na, const double* const* B,
+                                  int32_t nb, int64_t N, double* out, void* stream);
+
 /* ---- non-orthogonal bases (Sec. II.A) ----
  * Inverse factor of a symmetric positive-definite overlap matrix O (device
  * FP64 N x N): Z with Z^T O Z = I by the recursion X_n = Z_n^T O Z_n,

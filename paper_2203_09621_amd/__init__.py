@@ -6,7 +6,7 @@ loaded on first use of any entry point; a missing library raises ImportError."""
 
 _API = ("EXPORTS", "PRECISION", "DmptError", "dmpt_adjoint", "dmpt_batch_destroy",
         "dmpt_batch_info", "dmpt_batch_init", "dmpt_batch_response", "dmpt_congruence",
-        "dmpt_contract", "dmpt_cpscf", "dmpt_inverse_factor", "solve_nonorth",
+        "dmpt_contract", "dmpt_contract_noalloc", "dmpt_cpscf", "dmpt_inverse_factor", "solve_nonorth",
         "dmpt_destroy",
         "dmpt_gershgorin",
         "dmpt_init", "dmpt_layer_products", "dmpt_layer_trace", "dmpt_plan_rounds", "dmpt_plan_layer",

@@ -22,7 +22,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 
 # every entry point declared in include/dmpt.h
 EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_response",
-           "dmpt_response2", "dmpt_contract", "dmpt_inverse_factor", "dmpt_congruence",
+           "dmpt_response2", "dmpt_contract", "dmpt_contract_noalloc", "dmpt_inverse_factor", "dmpt_congruence",
            "dmpt_cpscf", "dmpt_adjoint", "dmpt_response_adjoint", "dmpt_destroy",
            "dmpt_batch_init", "dmpt_batch_response", "dmpt_batch_info", "dmpt_batch_destroy",
            "dmpt_status_str", "dmpt_last_error", "dmpt_layer_products", "dmpt_layer_trace",
@@ -102,6 +102,8 @@ def _load():
     lib.dmpt_contract.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32, c_int64,
                                   POINTER(c_double), c_void_p]
     lib.dmpt_contract.restype = c_int32
+    lib.dmpt_contract_noalloc.argtypes = lib.dmpt_contract.argtypes
+    lib.dmpt_contract_noalloc.restype = c_int32
     lib.dmpt_cpscf.argtypes = [c_void_p, c_void_p, _FIELD_FN, c_void_p, c_double, c_double,
                                c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_int32),
                                POINTER(c_double), POINTER(DmptStats)]
@@ -267,6 +269,22 @@ def dmpt_contract(As, Bs, stream=None):
     _check(LIB.dmpt_contract((c_void_p * na)(*[_dev(a, "A").value for a in As]), na,
                              (c_void_p * nb)(*[_dev(b, "B").value for b in Bs]), nb, n, out,
                              _stream(stream)))
+    return np.array(out[:]).reshape(na, nb)
+
+
+def dmpt_contract_noalloc(As, Bs, stream=None):
+    """dmpt_contract_noalloc: as dmpt_contract, with the partial sums in the
+    library's fixed device scratch (no allocation; at most 64 pairs)."""
+    import numpy as np
+    na, nb = len(As), len(Bs)
+    n = As[0].shape[0]
+    for m in list(As) + list(Bs):
+        if tuple(m.shape) != (n, n):
+            raise ValueError("every matrix must be N x N")
+    out = (c_double * (na * nb))()
+    _check(LIB.dmpt_contract_noalloc((c_void_p * na)(*[_dev(a, "A").value for a in As]), na,
+                                     (c_void_p * nb)(*[_dev(b, "B").value for b in Bs]), nb, n,
+                                     out, _stream(stream)))
     return np.array(out[:]).reshape(na, nb)
 
 

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1107,6 +1108,74 @@ dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* cons
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(part);
   (void)hipFree(dev);
+  return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
+}
+
+// ------------------------------------------------ contraction without allocation
+// Device scratch of dmpt_contract_noalloc: kNoAllocPairs blocks of kRedBlocks
+// FP64 partials, then one FP64 result per pair (520 KiB).  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// the name is only a host-side stand-in: kernels and copies get the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr int kNoAllocPairs = 64;
+static __device__ __align__(256) double scratch[(size_t)kNoAllocPairs * kRedBlocks + kNoAllocPairs];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// Device address of the scratch array on the current device, looked up once
+// per device (with that device current) and kept.
+dmpt_status scratch_address(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(DMPT_EHIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DMPT_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(DMPT_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+    if (!p) return fail(DMPT_EHIP, "scratch address: NULL");
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return DMPT_OK;
+}
+
+}  // namespace
+
+dmpt_status dmpt_contract_noalloc(const double* const* A, int32_t na, const double* const* B,
+                                  int32_t nb, int64_t N, double* out, void* stream) {
+  if (!A || !B || !out || na < 1 || nb < 1 || N < 1)
+    return fail(DMPT_EINVAL, "bad arguments");
+  if ((int64_t)na * nb > kNoAllocPairs)
+    return fail(DMPT_EINVAL, "contract_noalloc: na * nb = " + std::to_string((int64_t)na * nb) +
+                                 " exceeds the scratch limit of " + std::to_string(kNoAllocPairs) +
+                                 " pairs");
+  for (int i = 0; i < na; ++i)
+    if (!A[i] || (uintptr_t)A[i] % 16) return fail(DMPT_EINVAL, "A[a] NULL or not 16-byte aligned");
+  for (int i = 0; i < nb; ++i)
+    if (!B[i] || (uintptr_t)B[i] % 16) return fail(DMPT_EINVAL, "B[b] NULL or not 16-byte aligned");
+  double* base = nullptr;
+  const dmpt_status st = scratch_address(&base);
+  if (st != DMPT_OK) return st;
+  // every block writes its partial and the final kernel its result, so
+  // nothing in the scratch needs clearing
+  double* part = base;
+  double* dev = base + (size_t)kNoAllocPairs * kRedBlocks;
+  hipStream_t s = (hipStream_t)stream;
+  const int np = na * nb;
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < na && e == hipSuccess; ++a)
+    for (int b = 0; b < nb && e == hipSuccess; ++b)
+      e = launch_contract(A[a], B[b], N, part + (size_t)(a * nb + b) * kRedBlocks,
+                          dev + a * nb + b, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dev, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? DMPT_OK : fail(DMPT_EHIP, hipGetErrorString(e));
 }
 

@@ -211,7 +211,8 @@ __global__ void __launch_bounds__(kBlk) k_b_predecide(const BatchProblem* P, con
 __global__ void __launch_bounds__(kBlk) k_b_postdecide(const BatchProblem* P, const double* part_f,
                                                       const double* part_m, int t) {
   const BatchProblem& b = P[blockIdx.x];
-  postdecide_body(b.st, b.items, b.n_items, part_f + b.slot_first, part_m + b.slot_first, t);
+  postdecide_body(b.st, b.items, b.n_items, part_f + b.slot_first, part_m + b.slot_first, t,
+                  (int)blockIdx.x);
 }
 
 // ------------------------------------------------------------------ outputs
@@ -369,8 +370,10 @@ void batch_free(dmpt_batch* b) {
 hipError_t build_class_items(dmpt_batch* b, int threshold) {
   // Per class: problems in order of decreasing cost (products times k-tiles
   // over their tiles), their items dealt in balanced rounds over the launch's
-  // workgroups.  Each problem's items stay in order and contiguous apart from
-  // placeholders, which the kernels and the decisions skip.
+  // workgroups (the 128-row class per XCD, below).  Each problem's items keep
+  // their order; the range between its first and last position may hold
+  // placeholders and other problems' items, which the kernels and the
+  // decisions skip.
   std::vector<TileItem> cls[2];
   std::vector<int> first(b->count), count(b->count), which(b->count);
   std::vector<std::vector<TileItem>> own(b->count);
@@ -401,7 +404,46 @@ hipError_t build_class_items(dmpt_batch* b, int threshold) {
     }
     const int cap = (c ? 2 : 1) * b->cus;
     const int grid = (int)std::min<size_t>(list.size(), (size_t)cap);
-    const std::vector<int32_t> order = balanced_rounds(cost, grid, 2 * list.size());
+    std::vector<int32_t> order;
+    if (c == 1 && grid == cap && grid % kXcds == 0) {
+      // Problems to XCDs by decreasing cost (each to the least-loaded XCD),
+      // so that a problem's operand panels are fetched into one L2; each
+      // XCD's items sorted by length (stable: problem and band order kept)
+      // and dealt in balanced rounds over the XCD's slots (slot s runs on XCD
+      // s / (grid / 8)), so that items running side by side have equal
+      // length and step through k together.  The layer's partial slots
+      // follow the positions, so the decisions see the same values.
+      const int per = grid / kXcds;
+      std::vector<std::vector<int32_t>> seq(kXcds);   // list indices per XCD
+      std::vector<int64_t> load(kXcds, 0);
+      size_t li = 0;
+      for (int p : probs) {
+        int x = 0;
+        for (int y = 1; y < kXcds; ++y)
+          if (load[y] < load[x]) x = y;
+        load[x] += total[p];
+        for (size_t i = 0; i < own[p].size(); ++i) seq[x].push_back((int32_t)(li + i));
+        li += own[p].size();
+      }
+      size_t rounds = 0;
+      std::vector<std::vector<int32_t>> plan(kXcds);
+      for (int x = 0; x < kXcds; ++x) {
+        std::stable_sort(seq[x].begin(), seq[x].end(),
+                         [&](int32_t u, int32_t v) { return cost[u] > cost[v]; });
+        std::vector<int64_t> cx(seq[x].size());
+        for (size_t i = 0; i < cx.size(); ++i) cx[i] = cost[seq[x][i]];
+        plan[x] = balanced_rounds(cx, per, 2 * cx.size());
+        rounds = std::max(rounds, (plan[x].size() + per - 1) / per);
+      }
+      order.assign(rounds * grid, -1);
+      for (int x = 0; x < kXcds; ++x)
+        for (size_t q = 0; q < plan[x].size(); ++q)
+          if (plan[x][q] >= 0) order[(q / per) * grid + x * per + q % per] = seq[x][plan[x][q]];
+      while (!order.empty() && order.back() < 0) order.pop_back();
+      if (order.size() > 2 * list.size()) order = balanced_rounds(cost, grid, 2 * list.size());
+    } else {
+      order = balanced_rounds(cost, grid, 2 * list.size());
+    }
     std::vector<int> lo(b->count, -1), hi(b->count, -1);
     for (size_t q = 0; q < order.size(); ++q) {
       TileItem it;

@@ -336,7 +336,8 @@ static __device__ void decide1_body(LayerState* st, const Partials& pr, int spli
 // ||S1_j - X1_j||_F^2 (after D0) and max|S1_j,n|.  Outputs skipped this layer
 // are ignored.
 static __device__ void postdecide_body(LayerState* st, const TileItem* items, int n_items,
-                                       const double* part_f, const double* part_m, int lo_shift) {
+                                       const double* part_f, const double* part_m, int lo_shift,
+                                       int prob = 0) {
   if (st->done) return;
   const int k = st->k;
   const int xc = st->x_computed;
@@ -349,6 +350,7 @@ static __device__ void postdecide_body(LayerState* st, const TileItem* items, in
 #pragma unroll
   for (int j = 0; j < kMaxK; ++j) m[j] = 0.0;
   for (int i = threadIdx.x; i < n_items; i += kBlk) {
+    if (items[i].prob != prob) continue;       // another problem's item inside this range
     const int o = items[i].out;
     const double pf = part_f[i];
     if (o == 0) {

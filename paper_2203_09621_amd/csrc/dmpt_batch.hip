@@ -416,18 +416,24 @@ hipError_t build_class_items(dmpt_batch* b, int threshold) {
       const int per = grid / kXcds;
       std::vector<std::vector<int32_t>> seq(kXcds);   // list indices per XCD
       std::vector<int64_t> load(kXcds, 0);
+      int64_t all = 0;
       size_t li = 0;
       for (int p : probs) {
         int x = 0;
         for (int y = 1; y < kXcds; ++y)
           if (load[y] < load[x]) x = y;
         load[x] += total[p];
+        all += total[p];
         for (size_t i = 0; i < own[p].size(); ++i) seq[x].push_back((int32_t)(li + i));
         li += own[p].size();
       }
+      // too few problems to load every XCD evenly: the plain deal over all
+      // workgroups (a few large problems would otherwise leave XCDs idle)
+      const int64_t most = *std::max_element(load.begin(), load.end());
+      const bool even = 20 * most <= 21 * ((all + kXcds - 1) / kXcds);
       size_t rounds = 0;
       std::vector<std::vector<int32_t>> plan(kXcds);
-      for (int x = 0; x < kXcds; ++x) {
+      for (int x = 0; x < kXcds && even; ++x) {
         std::stable_sort(seq[x].begin(), seq[x].end(),
                          [&](int32_t u, int32_t v) { return cost[u] > cost[v]; });
         std::vector<int64_t> cx(seq[x].size());
@@ -435,12 +441,13 @@ hipError_t build_class_items(dmpt_batch* b, int threshold) {
         plan[x] = balanced_rounds(cx, per, 2 * cx.size());
         rounds = std::max(rounds, (plan[x].size() + per - 1) / per);
       }
-      order.assign(rounds * grid, -1);
-      for (int x = 0; x < kXcds; ++x)
+      order.assign(even ? rounds * grid : 0, -1);
+      for (int x = 0; x < kXcds && even; ++x)
         for (size_t q = 0; q < plan[x].size(); ++q)
           if (plan[x][q] >= 0) order[(q / per) * grid + x * per + q % per] = seq[x][plan[x][q]];
       while (!order.empty() && order.back() < 0) order.pop_back();
-      if (order.size() > 2 * list.size()) order = balanced_rounds(cost, grid, 2 * list.size());
+      if (!even || order.size() > 2 * list.size())
+        order = balanced_rounds(cost, grid, 2 * list.size());
     } else {
       order = balanced_rounds(cost, grid, 2 * list.size());
     }

@@ -133,3 +133,28 @@ def test_batch_full_equals_single_solves(dm, full_batch):
         worst = max(worst, d)
         assert d <= 1e-6, (i, p.N, d)
     print(f"512 problems vs single solves: worst difference {worst:.2e}", flush=True)
+
+
+def test_batch_ragged_sizes(dm):
+    """Sizes that are not multiples of 16 or 32 (partial 128-row tiles, the k
+    range rounded up to 32 inside a 256-padded panel layout), 1-3
+    perturbations, against the oracle and against the same problems solved
+    alone (equal bitwise: only exact zeros differ in the k range)."""
+    from oracle import exact
+    from workloads import dense_gapped_problem
+    sizes = [37, 100, 129, 257, 300, 511, 513]
+    probs = [dense_gapped_problem(n, n // 2 + (i % 3) - 1, 0.6, 900 + n, h1="diag",
+                                  k=1 + i % 3) for i, n in enumerate(sizes)]
+    (res,), info = _run(dm, probs)
+    P0, P1, st, _ = res
+    for i, p in enumerate(probs):
+        print(f"ragged batch N={p.N} nocc={p.nocc} k={p.k}", flush=True)
+        r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+        e = max([exact.rel_fro(P0[i], r0)] + [exact.rel_fro(a, b) for a, b in zip(P1[i], r1s)])
+        assert st[i]["converged"] and e < TOL, (p.N, e)
+        q0, q1s, sst = dm.solve(_cuda(p.H0), [_cuda(h) for h in p.H1], p.nocc,
+                                precision="split_bf16")
+        assert st[i]["layers"] == sst["layers"]
+        assert np.array_equal(P0[i], q0.cpu().numpy())
+        for a, b in zip(P1[i], q1s):
+            assert np.array_equal(a, b.cpu().numpy())

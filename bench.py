@@ -9,11 +9,15 @@ Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 
-  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4] [--precision P]
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|second|nonorth|cpscf]
+                  [--precision P]
                   [--no-fp64] [--no-cpu] [--cpu-sample] [--no-oracle]
 
 Workload c4 is the batched form: 512 problems of uneven size in one
 graph-captured response per step (split BF16 unless --precision says otherwise).
+c5 is the forward and adjoint at N = 4096.  second, nonorth and cpscf measure
+the wider rows at N = 4096: the second-order response, a non-orthogonal basis
+(inverse factor, congruences, response) and the self-consistent loop.
 """
 from __future__ import annotations
 
@@ -355,6 +359,240 @@ def batch_main(args, torch, dm):
     print(json.dumps(out), flush=True)
 
 
+def _host_cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
+
+
+def _timed_steps(torch, args, step, label):
+    """W untimed steps, then K timed ones between device synchronisations."""
+    for w in range(args.warmup):
+        step()
+        log(f"{label} warmup {w} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / args.steps, runs
+
+
+def second_main(args, torch, dm):
+    """Second-order response (the paper's k = 2 chain, dmpt_response2) at
+    N = 4096: configuration 5's H0 and dense H1 with a dense second-order term
+    H2 ~ N(0, 0.01^2) in H(l) = H0 + l H1 + l^2 H2.  One step =
+    set_hamiltonian + response2 (P0, P1, P2)."""
+    from oracle import exact
+    from workloads import config5, sym_normal
+    prec = args.precision or "split_fp16"
+    p = config5()
+    h2 = sym_normal(np.random.default_rng(1007), p.N, 0.01)
+    dev = torch.device("cuda:0")
+    H0, H1, H2 = (torch.from_numpy(a).to(dev) for a in (p.H0, p.H1[0], h2))
+    P0, P1, P2 = torch.empty_like(H0), torch.empty_like(H0), torch.empty_like(H0)
+    ctx = dm.dmpt_init(H0, p.nocc, k_max=2, precision=prec, timing=True)
+
+    def step():
+        dm.dmpt_set_hamiltonian(ctx, H0)
+        return dm.dmpt_response2(ctx, H1, H2, P0, P1, P2)[3]
+
+    ms, stats = _timed_steps(torch, args, step, "second")
+    st = stats[-1]
+    L, n = st["layers"], p.N
+    mult = 3.0 if prec.startswith("split") else 1.0
+    ends = [d if d > 0 else L for d in (list(st["d1_layer"]) + [0, 0])[:2]]
+    # per layer: X = S^2 (N^3/2, through the D0 layer), X1 = S S1 + S1 S (N^3
+    # through its stop layer), X2 = S1 S1 + S S2 + S2 S (3 N^3/2 through its own)
+    alg = sum(2.0 * mult * ((0.5 * n ** 3 if l <= st["x_layers"] else 0.0)
+                            + (n ** 3 if l <= ends[0] else 0.0)
+                            + (1.5 * n ** 3 if l <= ends[1] else 0.0)) for l in range(1, L + 1))
+    prod_ms = sum(s["product_ms"] for s in stats)
+    launches = sum(s["product_launches"] for s in stats)
+    achieved = alg * args.steps / (prod_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    out = {
+        "metric": METRIC, "value": round(1e3 / ms, 4),
+        "unit": "second-order responses/s (P0, P1, P2 at N = 4096)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"split_fp16": "f16", "split_bf16": "bf16", "fp32": "f32", "fp64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "second_order_N4096", "N": n, "nocc": p.nocc, "precision": prec,
+                   "layers": L, "d0_layer": st["d0_layer"], "d1_layer": ends[0],
+                   "d2_layer": ends[1]},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "k_products_split" if prec.startswith("split")
+                     else "k_products_direct",
+                     "avg_launch_ms": round(prod_ms / max(launches, 1), 4), "launches": launches},
+    }
+    if prec.startswith("split"):
+        out["roofline"]["measured_ceiling"] = mfma_ceiling(dm, prec, achieved)
+    dm.dmpt_destroy(ctx)
+    if not (args.no_oracle and args.no_cpu):
+        t = time.perf_counter()
+        r0, r1, r2 = exact.second_order_response(p.H0, p.H1[0], h2, p.nocc)
+        t_or = time.perf_counter() - t
+        e = [exact.rel_fro(a.cpu().numpy(), b) for a, b in ((P0, r0), (P1, r1), (P2, r2))]
+        log(f"oracle {t_or:.1f} s; errors P0 {e[0]:.2e} P1 {e[1]:.2e} P2 {e[2]:.2e}")
+        if not args.no_oracle:
+            out["rel_fro_err"] = {"P0": e[0], "P1": e[1], "P2": e[2]}
+        if not args.no_cpu:
+            out["cpu_baseline"] = {"value": round(1.0 / t_or, 4), "unit": out["unit"],
+                                   "cores": _host_cores(), "kind": "oracle",
+                                   "sample": f"exact FP64 second-order oracle (eigh + "
+                                             f"sum-over-states P1, P2) at N = {n}: {t_or:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+def nonorth_main(args, torch, dm):
+    """Non-orthogonal basis (Sec. II.A) at N = 4096: the inverse factor
+    Z = O^{-1/2} by the paper's recursion and the congruences Z H Z (FP64 MFMA
+    products), the response in the orthogonal basis (split FP16) and the
+    congruences back, one step each time."""
+    from oracle import exact
+    from workloads import nonorth_problem
+    prec = args.precision or "split_fp16"
+    oprec = "fp64"
+    p = nonorth_problem(4096, 2048, 0.5, 1008, k=1)
+    n = p.N
+    dev = torch.device("cuda:0")
+    H0, H1, O = (torch.from_numpy(a).to(dev) for a in (p.H0, p.H1[0], p.O))
+    Z, Hp, H1p = torch.empty_like(H0), torch.empty_like(H0), torch.empty_like(H0)
+    P0, P1 = torch.empty_like(H0), torch.empty_like(H0)
+    P0p, P1p = torch.empty_like(H0), torch.empty_like(H0)
+    ctx = None
+
+    def step():
+        # every library call returns after its stream has synchronised, so
+        # host timers bracket the device work of each phase
+        nonlocal ctx
+        t0 = time.perf_counter()
+        _, iters, _ = dm.dmpt_inverse_factor(O, precision=oprec, Z=Z)
+        dm.dmpt_congruence(Z, H0, precision=oprec, out=Hp)
+        dm.dmpt_congruence(Z, H1, precision=oprec, out=H1p)
+        t1 = time.perf_counter()
+        if ctx is None:
+            ctx = dm.dmpt_init(Hp, p.nocc, k_max=1, precision=prec, timing=True)
+        dm.dmpt_set_hamiltonian(ctx, Hp)
+        st = dm.dmpt_response(ctx, [H1p], P0p, [P1p])[2]
+        t2 = time.perf_counter()
+        dm.dmpt_congruence(Z, P0p, precision=oprec, out=P0)
+        dm.dmpt_congruence(Z, P1p, precision=oprec, out=P1)
+        t3 = time.perf_counter()
+        return iters, st, ((t1 - t0) + (t3 - t2)) * 1e3
+
+    ms, runs = _timed_steps(torch, args, step, "nonorth")
+    iters, st, _ = runs[-1]
+    ortho_ms = float(np.mean([r[2] for r in runs]))
+    # FP64 products of one step: per residual check Y = Z O (N^3) and X = Y Z
+    # (N^3/2, symmetric), per update X^2 and Z Q (N^3/2 each); four congruences
+    # Z A Z of N^3 + N^3/2
+    ortho_flops = 2.0 * n ** 3 * ((iters + 1) * 1.5 + iters * 1.0 + 4 * 1.5)
+    achieved = ortho_flops / (ortho_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(1e3 / ms, 4),
+        "unit": "non-orthogonal responses/s (inverse factor, congruences, P0, P1 at N = 4096)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f16", "data": "synthetic",
+        "config": {"workload": "nonorth_N4096", "N": n, "nocc": p.nocc, "ortho_precision": oprec,
+                   "response_precision": prec, "inverse_factor_updates": iters,
+                   "layers": st["layers"]},
+        "ortho_ms": round(ortho_ms, 3), "response_ms": round(st["ms"], 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
+                     "peak": PEAK_TFLOPS[oprec], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS[oprec], 4), "traffic": None,
+                     "kernel": "k_products_direct<double> (inverse factor and congruences "
+                               "over their host-timed span, which also holds the per-update "
+                               "residual check and its host read: a lower bound)",
+                     "measured_ceiling": mfma_ceiling(dm, oprec, achieved)},
+    }
+    dm.dmpt_destroy(ctx)
+    if not (args.no_oracle and args.no_cpu):
+        t = time.perf_counter()
+        r0, r1s = exact.generalized_solve(p.H0, p.O, p.H1, p.nocc)
+        t_or = time.perf_counter() - t
+        e0, e1 = exact.rel_fro(P0.cpu().numpy(), r0), exact.rel_fro(P1.cpu().numpy(), r1s[0])
+        log(f"oracle {t_or:.1f} s; errors P0 {e0:.2e} P1 {e1:.2e}")
+        if not args.no_oracle:
+            out["rel_fro_err"] = {"P0": e0, "P1": e1}
+        if not args.no_cpu:
+            out["cpu_baseline"] = {"value": round(1.0 / t_or, 4), "unit": out["unit"],
+                                   "cores": _host_cores(), "kind": "oracle",
+                                   "sample": f"exact FP64 generalised oracle (LAPACK sygvd + "
+                                             f"sum-over-states) at N = {n}: {t_or:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+def cpscf_main(args, torch, dm):
+    """Self-consistent first-order response (Sec. V.B coupled-perturbed loop,
+    dmpt_cpscf) at N = 4096 with the linear induced field G[P1] = c P1,
+    c = 0.15, on configuration 5's H0 and H1: fixed-point iterations of the
+    split-FP16 response until the relative change of P1 is below 1e-4 (the
+    response's own rounding noise, about 7e-5 at this size, is the floor)."""
+    from oracle import exact
+    from workloads import config5
+    prec = args.precision or "split_fp16"
+    c, tol = 0.15, 1e-4
+    p = config5()
+    dev = torch.device("cuda:0")
+    H0, H1 = torch.from_numpy(p.H0).to(dev), torch.from_numpy(p.H1[0]).to(dev)
+    ctx = dm.dmpt_init(H0, p.nocc, k_max=1, precision=prec, timing=True)
+
+    def step():
+        dm.dmpt_set_hamiltonian(ctx, H0)
+        return dm.dmpt_cpscf(ctx, H1, lambda p1, g: g.copy_(c * p1), tol=tol, max_iter=60)
+
+    ms, runs = _timed_steps(torch, args, step, "cpscf")
+    _, P1, iters, change, st = runs[-1]
+    n = p.N
+    ends = [d if d > 0 else st["layers"] for d in st["d1_layer"][:1]]
+    mult = 3.0 if prec.startswith("split") else 1.0
+    # the last response's product launches (each iteration runs the same layers)
+    alg = sum(2.0 * mult * ((0.5 * n ** 3 if l <= st["x_layers"] else 0.0)
+                            + (n ** 3 if l <= ends[0] else 0.0))
+              for l in range(1, st["layers"] + 1))
+    achieved = alg / (st["product_ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    out = {
+        "metric": METRIC, "value": round(1e3 / ms, 4),
+        "unit": "self-consistent responses/s (linear field, N = 4096)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"split_fp16": "f16", "split_bf16": "bf16", "fp32": "f32", "fp64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "cpscf_linear_N4096", "N": n, "nocc": p.nocc, "c": c, "tol": tol,
+                   "precision": prec, "field_evaluations": iters, "last_change": change,
+                   "layers_per_response": st["layers"]},
+        "ms_per_field_evaluation": round(ms / max(iters, 1), 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "k_products_split (the last response's launches, hipEvent-timed)",
+                     "avg_launch_ms": round(st["product_ms"] / max(st["product_launches"], 1), 4),
+                     "launches": st["product_launches"]},
+    }
+    if prec.startswith("split"):
+        out["roofline"]["measured_ceiling"] = mfma_ceiling(dm, prec, achieved)
+    dm.dmpt_destroy(ctx)
+    if not (args.no_oracle and args.no_cpu):
+        t = time.perf_counter()
+        ref = exact.cpscf_linear(p.H0, p.H1[0], p.nocc, c)
+        t_or = time.perf_counter() - t
+        e = exact.rel_fro(P1.cpu().numpy(), ref)
+        log(f"oracle {t_or:.1f} s; error P1 {e:.2e} after {iters} field evaluations")
+        if not args.no_oracle:
+            out["rel_fro_err"] = {"P1": e}
+        if not args.no_cpu:
+            out["cpu_baseline"] = {"value": round(1.0 / t_or, 4), "unit": out["unit"],
+                                   "cores": _host_cores(), "kind": "oracle",
+                                   "sample": f"exact FP64 fixed point (eigh + closed form "
+                                             f"H1~_ai/(e_i - e_a - c)) at N = {n}: {t_or:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def mfma_ceiling(dm, precision, achieved):
     """The split kernels' MFMA on random operands, back to back on every CU,
     measured right after the timed steps: the rate the chip sustains at the
@@ -372,7 +610,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4", "c5"])
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c2", "c1", "c4", "c5", "second", "nonorth", "cpscf"])
     ap.add_argument("--precision", default=None, choices=list(PEAK_TFLOPS))
     ap.add_argument("--batch-layers", type=int, default=100,
                     help="layers captured in the batched graph (c4)")
@@ -400,6 +639,12 @@ def main():
         return batch_main(args, torch, dm)
     if args.workload == "c5":
         return adjoint_main(args, torch, dm)
+    if args.workload == "second":
+        return second_main(args, torch, dm)
+    if args.workload == "nonorth":
+        return nonorth_main(args, torch, dm)
+    if args.workload == "cpscf":
+        return cpscf_main(args, torch, dm)
     if args.precision is None:
         args.precision = "split_fp16"
     t = time.perf_counter()

@@ -135,6 +135,23 @@ std::vector<TileItem> balanced_items(const std::vector<TileItem>& items, int gri
   return out;
 }
 
+// Tile edge of a single problem's fused layer launch for k responses.  The
+// 256-row launch (one workgroup per CU) needs several work units per CU to
+// balance: with (1 + 2k) T (T + 1) / 2 units of 256-row tiles over the CUs
+// below 3.4 per CU (N up to about 4096 for one response) the 128-row launch
+// (two workgroups per CU, four times the units) finishes first.  Measured,
+// split FP16, one box: N = 2048, k = 1: 9.0 against 14.5 ms per response;
+// N = 4096, k = 1: 35.0 against 34.8; N = 4096 second order: 64.1 against
+// 73.8; N = 6144: 99.3 against 93.6; N = 8192: 241 against 222.  Contexts
+// that keep adjoint checkpoints stay on 256-row tiles: the adjoint's forward
+// replay runs the same items through the 256-row non-fused kernel.
+int fused_tile(int64_t N, int k, int cus, bool adjoint) {
+  if (adjoint) return 256;
+  const int64_t T = (N + 255) / 256;
+  const double per_cu = (double)(1 + 2 * k) * T * (T + 1) / 2 / (cus > 0 ? cus : 256);
+  return per_cu < 3.4 ? 128 : 256;
+}
+
 // Item positions of the fused launch for k responses on `grid` workgroups,
 // and the per-item partial-slot capacity of a context sized for k_max.  The
 // plan of balanced_items keeps at most twice the item count (its limit), and
@@ -186,6 +203,7 @@ struct DevAlloc {
 struct dmpt_ctx {
   dmpt_precision prec;
   int64_t n, nocc, np, ld;
+  int ftile[kMaxK + 1];   // split forms: tile edge of the fused launch for k responses
   int k_max, max_layers, poll, check_sym;
   hipStream_t stream;
   LayerState* st;
@@ -414,15 +432,18 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
       if (e == hipSuccess) e = hipMemset(c->t3[j], 0, mat * eb);
     }
   }
-  const int T = (int)(c->np / tile);
   int cus = 0, dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
   for (int k = 1; k <= k_max; ++k) {
-    // split forms: one workgroup per CU in the fused launch, rounds balanced
-    std::vector<TileItem> items = split ? balanced_items(build_items(T, k), cus)
+    // split forms: the fused launch's tile and its rounds balanced over its
+    // workgroups (the 256-row launch runs one per CU, the 128-row one two)
+    c->ftile[k] = split ? fused_tile(N, k, cus, c->ckpt > 0) : tile;
+    const int T = split ? (int)((N + c->ftile[k] - 1) / c->ftile[k]) : (int)(c->np / tile);
+    const int fgrid = c->ftile[k] == 128 ? 2 * cus : cus;
+    std::vector<TileItem> items = split ? balanced_items(build_items(T, k), fgrid)
                                         : build_items(T, k);
     c->n_items[k] = (int)items.size();
     get((void**)&c->items[k], items.size() * sizeof(TileItem));
@@ -433,7 +454,8 @@ dmpt_status dmpt_init(dmpt_ctx** out, const double* H0, int64_t N, int64_t Nocc,
   if (split) {
     // one slot per item position of every k <= k_max (the plan's length is
     // not monotonic in k: placeholders of balanced rounds)
-    c->part_cap = fused_slot_capacity(T, k_max);
+    // slots for the larger of the two tilings' plans
+    c->part_cap = fused_slot_capacity((int)((N + 127) / 128), k_max);
     for (int k = 1; k <= k_max; ++k)
       if (c->n_items[k] > c->part_cap) return bail(DMPT_EINVAL, "item plan exceeds slot capacity");
     get((void**)&c->part_f, (size_t)c->part_cap * sizeof(double));
@@ -580,7 +602,7 @@ dmpt_status run_response(dmpt_ctx* c, const double* const* H1, int k1, bool orde
       HIPCHK(launch_trace_diag(prec, c->desc, c->tblocks, c->n_tblocks, c->part_tr, s));
       HIPCHK(launch_predecide(c->st, c->part_tr, c->n_tblocks, s));
       if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1)], s));
-      HIPCHK(launch_products_fused(prec, product_tile(prec), pa, s));
+      HIPCHK(launch_products_fused(prec, c->ftile[k], pa, s));
       if (c->timing) HIPCHK(hipEventRecord(c->pev[2 * (n - 1) + 1], s));
       HIPCHK(launch_postdecide(c->st, c->items[k], c->n_items[k], c->part_f, c->part_m, t, s));
     } else {

@@ -288,3 +288,53 @@ def test_persistent_loop_model(dm, N, k, k_max):
             pi = ((grow // PANEL_ROWS) * (Np // PANEL_K) + gcol // PANEL_K) * PANEL_ROWS * PANEL_K \
                 + (grow % PANEL_ROWS) * PANEL_K + gcol % PANEL_K
             assert gcol % PANEL_K + 4 <= PANEL_K and pi + 4 <= Np * Np
+
+
+@pytest.mark.parametrize("N,k,k_max", [(300, 1, 1), (2048, 1, 1), (4096, 2, 2), (3000, 3, 3),
+                                       (4096, 1, 8)])
+def test_persistent_loop_model_128(dm, N, k, k_max):
+    """The same walk for the 128-row fused launch that small single-problem
+    contexts (and the batch) use: 2 x 2 waves of 64 x 64, 32 KB stages, two
+    workgroups per CU (grid 512), tiles of 128 rows inside the 256-row panel
+    blocks, the k loop over N rounded up to 32, partial slots sized for the
+    128-row tiling."""
+    bm, grid = 128, 512
+    nt, ch = 256, 4
+    rows = 4 * bm
+    stage = rows * ch
+    rpl = nt // ch
+    loads = rows // rpl
+    Np = -(-N // 256) * 256
+    T, ld = -(-N // bm), Np + 128
+    items = layer_items(T, k)
+    cost = np.array([1 if o == 0 else 2 for o, _, _ in items], dtype=np.int64)
+    order = dm.dmpt_plan_rounds(cost, grid, cap=2 * len(cost))
+    n_pos, cap = dm.dmpt_plan_layer(T, k, k_max, grid)
+    assert len(order) == n_pos <= cap
+    g = min(n_pos, grid)
+    slots = [xcd_remap(b, g) for b in range(g)]
+    assert sorted(slots) == list(range(g))
+    real = order[order >= 0]
+    assert np.array_equal(real, np.arange(len(items)))
+    kblocks, kt = Np // 32, -(-N // 32)
+    tid = np.arange(nt)
+    lane, wave = tid % 64, tid // 64
+    lrow, lsl = tid // ch, tid % ch
+    csrc = lsl ^ ((lrow >> 2) & (ch - 1))
+    voff = lrow * 32 + csrc * 8
+    for i in range(loads):
+        arr = (i * rpl) // bm
+        assert arr < 4
+        dst = (i * rpl + wave * (64 // ch)) * ch + lane
+        assert dst.max() < stage
+        local = (i * rpl - arr * bm) * 32 + voff
+        assert local.max() + 8 <= 256 * 32          # inside one panel block
+    for idx in real:
+        out, ti, tj = items[idx]
+        for row0 in (ti * bm, tj * bm):
+            off = (row0 // 256) * kblocks * 8192 + (row0 % 256) * 32
+            assert off + (kt - 1) * 8192 + (bm - 1) * 32 + 32 <= Np * Np
+        assert tj * bm + bm <= Np and (tj * bm + bm - 1) * ld + tj * bm + bm <= Np * ld
+    # epilogue staging of the 128-row tile inside the launch's 2 x 32 KB
+    sr, pt = 64, bm + 4
+    assert sr * pt * 4 <= 2 * stage * 16

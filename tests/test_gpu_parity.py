@@ -206,3 +206,27 @@ def test_reported_idempotency_residuals(dm, precision):
     err1 = float(np.linalg.norm(x1 - (P0 @ P1 + P1 @ P0)))
     assert abs(idem0 - inv["idem_p0"]) <= err0 * (1 + 1e-9) + 1e-14
     assert abs(idem1 - inv["idem_p1"]) <= err1 * (1 + 1e-9) + 1e-14
+
+
+@pytest.mark.parametrize("n", [2048, 700])
+def test_tile_choice_does_not_change_results(dm, n):
+    """Small contexts run the fused layer on 128-row tiles, contexts that keep
+    adjoint checkpoints on 256-row tiles.  Every output element takes the same
+    operands, k order and MFMA sequence either way, so P0, P1 and the layer
+    counts agree bitwise."""
+    import torch
+    from workloads import dense_gapped_problem
+    p = dense_gapped_problem(n, n // 2, 0.5, 3100 + n, h1="dense", k=1)
+    H0, H1 = _cuda(p.H0), _cuda(p.H1[0])
+    outs = []
+    for ckpt in (0, 8):
+        ctx = dm.dmpt_init(H0, p.nocc, k_max=1, precision="split_bf16", ckpt_every=ckpt)
+        try:
+            P0, (P1,), st = dm.dmpt_response(ctx, [H1])
+            torch.cuda.synchronize()
+            outs.append((P0.cpu().numpy(), P1.cpu().numpy(), st["layers"], st["d0_layer"]))
+        finally:
+            dm.dmpt_destroy(ctx)
+    (a0, a1, la, da), (b0, b1, lb, db) = outs
+    assert (la, da) == (lb, db)
+    assert np.array_equal(a0, b0) and np.array_equal(a1, b1)

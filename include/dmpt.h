@@ -251,7 +251,7 @@ dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* cons
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, results and reduction order as
  * dmpt_contract (the results are bitwise the same), with its partial sums in a
- * fixed device array of the library (520 KiB per GPU, held until the process
+ * fixed device array of the library (512.5 KiB per GPU, held until the process
  * ends) instead of per-call buffers.  At most 64 pairs: na * nb > 64 returns
  * EINVAL.  Every call on a GPU shares that GPU's array: calls that overlap on
  * one GPU (several streams or threads at once) race and give undefined

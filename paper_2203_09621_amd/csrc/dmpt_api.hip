@@ -1135,7 +1135,7 @@ dmpt_status dmpt_contract(const double* const* A, int32_t na, const double* cons
 
 // ------------------------------------------------ contraction without allocation
 // Device scratch of dmpt_contract_noalloc: kNoAllocPairs blocks of kRedBlocks
-// FP64 partials, then one FP64 result per pair (520 KiB).  Every GPU the
+// FP64 partials, then one FP64 result per pair (512.5 KiB).  Every GPU the
 // library runs on holds its own copy until the process ends.  In host code
 // the name is only a host-side stand-in: kernels and copies get the device
 // address that hipGetSymbolAddress returns for the current device.

@@ -132,14 +132,13 @@ def test_adjoint_full_size(dm):
     assert e0 < TOL and e1 < TOL
 
 
-def test_adjoint_full_size_vs_fd(dm):
-    """N = 4096: the split-BF16 / FP32 adjoint against central differences
-    (h = 1e-5) of the FP64 GPU forward on 32 random entries of each gradient,
-    relative error of the sampled gradient vector within 1e-3."""
-    import torch
+@pytest.fixture(scope="module")
+def c5_fd(dm):
+    """Configuration 5 (N = 4096) and central differences (h = 1e-5) of the
+    FP64 GPU forward's L = Tr(P1 W) on 32 seeded entries (i <= j) of each
+    gradient."""
     from workloads import config5
     p = config5()
-    _, g0, g1, _, _ = _grads(dm, p, "split_bf16", 8)
     H0, H1, W = _cuda(p.H0), _cuda(p.H1[0]), _cuda(p.W)
     h = 1e-5
     rng = np.random.default_rng(23)
@@ -170,14 +169,28 @@ def test_adjoint_full_size_vs_fd(dm):
         lp = loss(dm.solve(bump(H0, i, j, h), [H1], p.nocc, precision="fp64")[1][0])
         lm = loss(dm.solve(bump(H0, i, j, -h), [H1], p.nocc, precision="fp64")[1][0])
         fd0.append((lp - lm) / (2 * h) / fac)
+    return p, pairs, np.array(fd0), np.array(fd1)
+
+
+# The workload's split-BF16 forward sets the gradients' error (about 7e-4
+# against the closed form, 9.6e-4 on these 32 entries).  The same check on
+# more precise forwards shows that the finite differences themselves are far
+# more accurate: split FP16 agrees to about 1.3e-4, FP64 to about 6e-7.
+@pytest.mark.parametrize("precision,tol", [("split_bf16", TOL), ("split_fp16", 5e-4),
+                                           ("fp64", 1e-5)])
+def test_adjoint_full_size_vs_fd(dm, c5_fd, precision, tol):
+    """N = 4096: the adjoint (checkpoints every 8 layers) against central
+    differences of the FP64 GPU forward on 32 random entries of each gradient,
+    relative error of the sampled gradient vector."""
+    p, pairs, fd0, fd1 = c5_fd
+    _, g0, g1, _, _ = _grads(dm, p, precision, 8)
     s0 = np.array([g0[i, j] for i, j in pairs])
     s1 = np.array([g1[i, j] for i, j in pairs])
-    fd0, fd1 = np.array(fd0), np.array(fd1)
     e0 = float(np.linalg.norm(s0 - fd0) / np.linalg.norm(fd0))
     e1 = float(np.linalg.norm(s1 - fd1) / np.linalg.norm(fd1))
-    print(f"adjoint N=4096 vs FD on 32 entries: dH0 {e0:.2e} dH1 {e1:.2e}", flush=True)
-    assert e0 < TOL and e1 < TOL
-    del torch
+    print(f"adjoint N=4096 {precision} vs FD on 32 entries: dH0 {e0:.2e} dH1 {e1:.2e}",
+          flush=True)
+    assert e0 < tol and e1 < tol
 
 
 def test_adjoint_dh0_vs_mixed_second_order(dm, c5_small):

@@ -297,6 +297,27 @@ std::vector<TileItem> triangle_items(int T, int k, int prob) {
   return v;
 }
 
+// Items of the pair launch: the tiles (ti, tj), tj >= ti, of each row band
+// two by two from the diagonal, an odd last one alone (tj2 = -1).
+std::vector<TileItem> pair_items(int T, int k, int prob) {
+  std::vector<TileItem> v;
+  auto add_out = [&](int out) {
+    for (int ti = 0; ti < T; ++ti)
+      for (int tj = ti; tj < T; tj += 2) {
+        TileItem it;
+        it.out = (int16_t)out;
+        it.prob = (int16_t)prob;
+        it.ti = ti;
+        it.tj = tj;
+        it.tj2 = tj + 1 < T ? tj + 1 : -1;
+        v.push_back(it);
+      }
+  };
+  for (int j = 0; j < k; ++j) add_out(1 + j);
+  add_out(0);
+  return v;
+}
+
 }  // namespace
 
 struct dmpt_batch {
@@ -321,7 +342,7 @@ struct dmpt_batch {
   double* part_m = nullptr;
   ProblemDesc* desc = nullptr;                 // per problem: buffers of the fused layer
   int threshold = 0;                           // problems with Np <= threshold use 128-row tiles
-  TileItem* items[2] = {nullptr, nullptr};     // [0]: 256-row tiles, [1]: 128-row tiles
+  TileItem* items[2] = {nullptr, nullptr};     // [0]: 256-row tiles, [1]: pairs of 128-row tiles
   int n_items[2] = {0, 0};
   int total_k = 0;
   int cus = 256;                               // compute units of the device
@@ -370,7 +391,8 @@ void batch_free(dmpt_batch* b) {
 hipError_t build_class_items(dmpt_batch* b, int threshold) {
   // Per class: problems in order of decreasing cost (products times k-tiles
   // over their tiles), their items dealt in balanced rounds over the launch's
-  // workgroups (the 128-row class per XCD, below).  Each problem's items keep
+  // workgroups (the 128-row class per XCD, below).  The 128-row class runs in
+  // pairs of tiles of one row band (k_products_pair).  Each problem's items keep
   // their order; the range between its first and last position may hold
   // placeholders and other problems' items, which the kernels and the
   // decisions skip.
@@ -385,7 +407,7 @@ hipError_t build_class_items(dmpt_batch* b, int threshold) {
     const int tile = c ? 128 : 256;
     const int T = (int)((bp.n + tile - 1) / tile);
     which[p] = c;
-    own[p] = triangle_items(T, bp.k, p);
+    own[p] = c ? pair_items(T, bp.k, p) : triangle_items(T, bp.k, p);
     for (const TileItem& it : own[p]) {
       own_cost[p].push_back((it.out == 0 ? 1 : 2) * ((int64_t)T * tile / kPanelK));
       total[p] += own_cost[p].back();
@@ -402,7 +424,7 @@ hipError_t build_class_items(dmpt_batch* b, int threshold) {
       list.insert(list.end(), own[p].begin(), own[p].end());
       cost.insert(cost.end(), own_cost[p].begin(), own_cost[p].end());
     }
-    const int cap = (c ? 2 : 1) * b->cus;
+    const int cap = b->cus;                  // one workgroup per CU in both launches
     const int grid = (int)std::min<size_t>(list.size(), (size_t)cap);
     std::vector<int32_t> order;
     if (c == 1 && grid == cap && grid % kXcds == 0) {
@@ -528,7 +550,7 @@ hipError_t launch_products_all(dmpt_batch* b, hipStream_t s) {
     a.items = b->items[1];
     a.n_items = b->n_items[1];
     a.slot_base = b->n_items[0];
-    e = launch_products_fused(b->prec, 128, a, s);
+    e = launch_products_pair(b->prec, a, s);
   }
   return e;
 }

@@ -537,6 +537,435 @@ k_products_split(const ProductArgs a) {
   }  // items
 }
 
+// ------------------------------------------------------------------ batched pairs
+// Barrier for hand-offs through the LDS: this wave's LDS accesses have
+// completed and the compiler keeps memory accesses on their side of it.
+// Outstanding global stores and direct-to-LDS loads are not waited for (a
+// workgroup fence would wait for all of them); callers wait for their loads
+// explicitly.  Global memory written in a launch is not read back in it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(LgkWait<0>::imm);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Fused layer products on items of two 128 x 128 tiles of one row band,
+// (ti, tj) and (ti, tj2): both read the A panels of band ti (rows of S, or of
+// S1_j for the second product of a response), so one k-tile loads A once for
+// both, 48 KB for 96 MFMAs per wave pair instead of 64 KB.  Eight waves of
+// 64 x 64 (waves with wn < 2 hold tile (ti, tj), the others (ti, tj2)), one
+// workgroup per CU and three LDS stages, so the loads of k-tile t + 3 go out
+// while tile t is multiplied and are waited for two tiles later: the batch's
+// small problems miss the L2 often, and one tile of lead time does not cover
+// that latency.  No barrier waits for global stores or for loads beyond the
+// one the pipeline needs (lds_barrier).  A band with an odd number of tiles
+// leaves one single tile (tj2 < 0): its second B panel repeats the first and
+// the waves of the right half only load and wait.  First-order items only
+// (X and X1_j).
+template <typename T16, int SWZ>
+__global__ void __launch_bounds__(8 * kWave)
+k_products_pair(const ProductArgs a) {
+  using S = Split16<T16>;
+  using V = typename S::V;
+  constexpr int BM = 128, BK = kPanelK, WGM = 2, WGN = 4, STAGES = 3;
+  constexpr int NT = WGM * WGN * kWave;
+  constexpr int WTM = 64, WTN = 64, FM = WTM / 32, FN = WTN / 32;
+  constexpr int CH = BK / 8;                 // 16-byte chunks per row of a k-tile
+  constexpr int NARR = 6;                    // A_hi | A_lo | B0_hi | B0_lo | B1_hi | B1_lo
+  constexpr int STAGE = NARR * BM * CH;      // chunks per pipeline stage
+  constexpr int RPW = kWave / CH;            // rows one wave fills per load instruction
+  constexpr int RPL = NT / CH;               // rows all waves fill per load round
+  constexpr int LOADS = NARR;                // load rounds per k-tile, one per array
+  constexpr int BN = 2 * BM;                 // columns of a pair
+  constexpr int SR = 32 * WGM;               // epilogue: tile rows staged per round
+  constexpr int PT = BN + 4;                 // epilogue: LDS row pitch (floats)
+  static_assert(RPL == BM, "one load round fills one array");
+  static_assert((RPL >> SWZ) % CH == 0, "swizzle must repeat every load round");
+  static_assert(kPanelRows % BM == 0 && BK == 32, "tile inside a panel block, two k steps");
+  static_assert(SR * PT * 4 <= STAGES * STAGE * 16, "epilogue staging fits in the operand LDS");
+  extern __shared__ u32x4 lds[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = uni(tid / kWave);
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int half = wn >> 1;
+  // Loads go straight from global memory into LDS: lane l of a wave writes
+  // 16-byte slot l of the wave's 1 KB destination (row lrow, slot lsl) and
+  // fetches the chunk whose XOR-swizzled position that slot is.
+  const int lrow = tid / CH, lsl = tid % CH;
+  const int csrc = lsl ^ ((lrow >> SWZ) & (CH - 1));
+  const int voff = lrow * kPanelK + csrc * 8;
+
+  // Operands of one item: panels per product p, Q<p> = [hi_A, lo_A, hi_B, lo_B]
+  // (X: S S;  X1_j: S S1_j, S1_j S), panel-major (the k-tile kt of row tile I is
+  // the contiguous block I * kblocks + kt of kPanelRows x kPanelK elements).
+  struct Ops {
+    TileItem it;
+    int sexp, kt_per, ktiles;
+    const uint16_t* q[4];                      // hi_S, lo_S, hi_T, lo_T (T = S1_j or S)
+    int64_t offa, offb0, offb1;
+  };
+  // The first item at or after position id (stepping by the grid) with work
+  // to do; false if there is none.
+  auto find = [&](int& id, Ops& o) -> bool {
+    for (; id < a.n_items; id += gridDim.x) {
+      o.it = a.items[id];
+      o.sexp = 0;
+      if (!item_active<true>(a, o.it, &o.sexp)) continue;
+      const ProblemDesc* pd = a.probs + o.it.prob;
+      const LayerState* fst = pd->state;
+      const int j = o.it.out - 1;
+      const int sp = fst->s_par;
+      const int lp = (fst->n - 1) & 1;         // S1_{n-1} split
+      const uint16_t* sh = (const uint16_t*)pd->s_hi[sp];
+      const uint16_t* sl = (const uint16_t*)pd->s_lo[sp];
+      const uint16_t* th = o.it.out != 0 ? (const uint16_t*)pd->s1_hi[j][lp] : sh;
+      const uint16_t* tl = o.it.out != 0 ? (const uint16_t*)pd->s1_lo[j][lp] : sl;
+      o.q[0] = sh; o.q[1] = sl; o.q[2] = th; o.q[3] = tl;
+      const int64_t kblocks = uni(pd->pdim / kPanelK);
+      auto block_of = [&](int64_t r0) {
+        return uni((r0 / kPanelRows) * kblocks * (kPanelRows * kPanelK) + (r0 % kPanelRows) * kPanelK);
+      };
+      const int tj2 = uni(o.it.tj2);
+      o.offa = block_of((int64_t)o.it.ti * BM);
+      o.offb0 = block_of((int64_t)o.it.tj * BM);
+      o.offb1 = block_of((int64_t)(tj2 < 0 ? o.it.tj : tj2) * BM);
+      o.kt_per = uni((int)(pd->kdim / BK));
+      o.ktiles = uni((o.it.out == 0 ? 1 : 2) * o.kt_per);
+      return true;
+    }
+    return false;
+  };
+  // k-tile t0 of an item; past the end the last tile is fetched again into a
+  // stage nobody reads any more.  One load round moves one array.
+  // The fetch plan in scalar registers: an item's values come back from
+  // memory in vector registers, and carried from one item to the next they
+  // stay there unless read out here once per item.
+  struct Plan {
+    const uint16_t* q[4];
+    int64_t offa, offb0, offb1;
+    int kt_per, ktiles;
+  };
+  auto plan_of = [&](const Ops& o) {
+    Plan pl;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pl.q[r] = uni(o.q[r]);
+    pl.offa = uni(o.offa);
+    pl.offb0 = uni(o.offb0);
+    pl.offb1 = uni(o.offb1);
+    pl.kt_per = uni(o.kt_per);
+    pl.ktiles = uni(o.ktiles);
+    return pl;
+  };
+  struct Fetch { const uint16_t* q[NARR]; u32x4* dst; };
+  auto prep = [&](const Plan& o, int t0) {
+    Fetch f;
+    const int t = t0 < o.ktiles ? t0 : o.ktiles - 1;
+    const int p = t >= o.kt_per;               // product 1: A = T, B = S
+    const int64_t kofs = (int64_t)(t - p * o.kt_per) * (kPanelRows * kPanelK);
+    const uint16_t* ah = p ? o.q[2] : o.q[0];
+    const uint16_t* al = p ? o.q[3] : o.q[1];
+    const uint16_t* bh = p ? o.q[0] : o.q[2];
+    const uint16_t* bl = p ? o.q[1] : o.q[3];
+    f.q[0] = ah + o.offa + kofs;
+    f.q[1] = al + o.offa + kofs;
+    f.q[2] = bh + o.offb0 + kofs;
+    f.q[3] = bl + o.offb0 + kofs;
+    f.q[4] = bh + o.offb1 + kofs;
+    f.q[5] = bl + o.offb1 + kofs;
+    f.dst = lds + (t0 % STAGES) * STAGE;
+    return f;
+  };
+  auto issue_round = [&](const Fetch& f, int i) {
+    u32x4* dst = f.dst + (i * RPL + wave * RPW) * CH;                  // wave-uniform
+    __builtin_amdgcn_global_load_lds((const void*)(f.q[i] + voff), (void*)dst, 16, 0, 0);
+  };
+  auto issue = [&](const Plan& o, int t0) {
+    const Fetch f = prep(o, t0);
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) issue_round(f, i);
+  };
+
+  // Fragment g of a 16-wide k step: hi_A m = g, lo_A m = g - FM,
+  // hi_B n = g - 2 FM, lo_B n = g - 2 FM - FN (B from this wave's half).
+  constexpr int NF = 2 * (FM + FN);
+  constexpr int NM = 3 * FM * FN;
+  static_assert(NM >= NF, "at least one MFMA per LDS read");
+  struct Frag { V ah[FM], al[FM], bh[FN], bl[FN]; };
+  auto read_one = [&](int stage, int kk, Frag& f, int g) {
+    const u32x4* base = lds + stage * STAGE;
+    const int c = kk * 2 + (lane >> 5);
+    const bool a_side = g < 2 * FM;
+    const int idx = a_side ? g % FM : (g - 2 * FM) % FN;
+    const bool lo = a_side ? g >= FM : g >= 2 * FM + FN;
+    const int R = a_side ? (lo ? BM : 0) + wm * WTM + idx * 32 + (lane & 31)
+                         : (2 + 2 * half + (lo ? 1 : 0)) * BM + (wn & 1) * WTN + idx * 32 +
+                               (lane & 31);
+    const int cc = c ^ ((R >> SWZ) & (CH - 1));
+    const V v = __builtin_bit_cast(V, base[R * CH + cc]);
+    if (a_side) {
+      if (lo) f.al[idx] = v; else f.ah[idx] = v;
+    } else {
+      if (lo) f.bl[idx] = v; else f.bh[idx] = v;
+    }
+  };
+  auto read = [&](int stage, int kk, Frag& f) {
+#pragma unroll
+    for (int g = 0; g < NF; ++g) read_one(stage, kk, f, g);
+  };
+
+  // Persistent grid: round r hands item r * G + slot to this workgroup; the
+  // slots of one XCD are contiguous.
+  const int slot = xcd_remap(blockIdx.x, gridDim.x);
+  Ops cur;
+  for (int id = slot; find(id, cur); id += gridDim.x) {
+  const Plan pl = plan_of(cur);
+  const TileItem it = cur.it;
+  const int j = it.out - 1;
+  const ProblemDesc* pd = a.probs + it.prob;
+  const LayerState* fst = pd->state;
+  const int64_t ld = pd->ld, pdim = pd->pdim;
+  const int tj2 = uni(it.tj2);
+  const bool single = tj2 < 0;
+  const bool live = !(single && half);       // wave-uniform
+  const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BM;
+  const int64_t row_b1 = single ? row_b0 : (int64_t)tj2 * BM;
+  const int ktiles = pl.ktiles;
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int m = 0; m < FM; ++m)
+#pragma unroll
+    for (int n = 0; n < FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.0f;
+
+  // MFMA q of a k step, per accumulator in the order hi*hi (A scaled by 2^t),
+  // hi*lo, lo*hi: q = prod * FM * FN + m * FN + n.
+  auto mma_one = [&](const Frag& f, V* as, int q) {
+    const int prod = q / (FM * FN), m = (q / FN) % FM, n = q % FN;
+    if (prod == 0) {
+      if (n == 0) as[m] = S::up(f.ah[m]);
+      acc[m][n] = S::mma(as[m], f.bh[n], acc[m][n]);
+    } else if (prod == 1) {
+      acc[m][n] = S::mma(f.ah[m], f.bl[n], acc[m][n]);
+    } else {
+      acc[m][n] = S::mma(f.al[m], f.bh[n], acc[m][n]);
+    }
+  };
+  // One k step of MFMAs on cur in NF groups; group g also reads fragment g of
+  // nxt and issues its share of the load rounds.
+  auto step = [&](const Frag& fc, Frag& fn, int rstage, int rkk, const Fetch* fetch) {
+    V as[FM];
+#pragma unroll
+    for (int g = 0; g < NF; ++g) {
+      read_one(rstage, rkk, fn, g);
+      if (fetch) {
+#pragma unroll
+        for (int i = (g * LOADS) / NF; i < ((g + 1) * LOADS) / NF; ++i) issue_round(*fetch, i);
+      }
+#pragma unroll
+      for (int q = (g * NM) / NF; q < ((g + 1) * NM) / NF; ++q) mma_one(fc, as, q);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  // Software pipeline over three stages.  At the barrier in the middle of k-tile t every wave has read all of tile t
+  // (its stage may be refilled) and its loads of tile t + 1 have landed
+  // (loads complete in order: only tile t + 2's may still be outstanding);
+  // the loads of tile t + 3 then go out.  Waves without a tile run the same
+  // loads and barriers and nothing else (a separate copy of the loop, so that
+  // no branch sits between the MFMAs).
+  issue(pl, 0);
+  issue(pl, 1);
+  issue(pl, 2);
+  __builtin_amdgcn_s_waitcnt(VmWait<2 * LOADS>::imm);
+  lds_barrier();
+  if (live) {
+    Frag f0, f1;
+    read(0, 0, f0);
+#pragma unroll 1
+    for (int t = 0; t < ktiles; ++t) {
+      __builtin_amdgcn_s_waitcnt(LgkWait<0>::imm);
+      step(f0, f1, t % STAGES, 1, nullptr);
+      const Fetch fe = prep(pl, t + 3);
+      __builtin_amdgcn_s_waitcnt(VmWait<LOADS>::imm);
+      lds_barrier();
+      step(f1, f0, (t + 1) % STAGES, 0, &fe);
+    }
+  } else {
+#pragma unroll 1
+    for (int t = 0; t < ktiles; ++t) {
+      const Fetch fe = prep(pl, t + 3);
+      __builtin_amdgcn_s_waitcnt(VmWait<LOADS>::imm);
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < LOADS; ++i) issue_round(fe, i);
+    }
+  }
+  // the refetches past the end land before the LDS is reused
+  __builtin_amdgcn_s_waitcnt(0);
+  lds_barrier();
+
+  // Fused epilogue, as in k_products_split, over the 256 columns of the pair:
+  // column lc of the staged rows is column lc % 128 of tile (ti, tj) (lc < 128)
+  // or of tile (ti, tj2).  Only tile (ti, tj) can lie on the diagonal.
+  const float scale = ldexpf(1.0f, -(S::kShift + cur.sexp));
+  const bool diag0 = it.ti == it.tj;
+  constexpr int ITER = SR * BN / (4 * NT);   // float4 groups per thread and round
+  constexpr int G = ITER < 4 ? ITER : 4;
+  static_assert(SR * BN % (4 * NT) == 0 && ITER % G == 0, "whole float4 groups per thread");
+  float* T = (float*)lds;
+  const int sig = fst->sigma_cur;
+  const bool isx = it.out == 0;
+  const bool upd = isx ? fst->upd_s0 != 0 : true;
+  const bool diff = isx ? !upd : fst->d0 != 0;
+  const bool need_old = diff || sig < 0;
+  const int cpar = fst->n & 1;
+  const float* Mr = isx ? pd->s_master : pd->s1m[j][cpar ^ 1];
+  float* Mw = isx ? pd->s_master : pd->s1m[j][cpar];
+  uint16_t* Hw = (uint16_t*)(isx ? pd->s_hi[fst->s_par ^ 1] : pd->s1_hi[j][cpar]);
+  uint16_t* Lw = (uint16_t*)(isx ? pd->s_lo[fst->s_par ^ 1] : pd->s1_lo[j][cpar]);
+  const int esplit = isx ? 0 : fst->s1_exp_next[j];
+  typedef uint16_t U4 __attribute__((ext_vector_type(4)));
+  double pf = 0.0;
+  float pm = 0.0f;
+#pragma unroll
+  for (int m = 0; m < FM; ++m) {
+    if (live) {
+#pragma unroll
+      for (int n = 0; n < FN; ++n)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          T[row * PT + wn * WTN + n * 32 + (lane & 31)] = acc[m][n][r] * scale;
+        }
+    }
+    lds_barrier();
+    // direct block: T row tr is tile row (tr / 32) * WTM + m * 32 + tr % 32;
+    // a thread's column lc is the same in every group (NT * 4 is a multiple of BN)
+#pragma unroll 1
+    for (int g0 = 0; g0 < ITER; g0 += G) {
+      f32x4 sov[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int e = (tid + (g0 + i) * NT) * 4;
+        const int tr = e / BN, lc = e % BN;
+        const int h = lc / BM, lcl = lc % BM;
+        const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
+        const int64_t col0 = h ? row_b1 : row_b0;
+        sov[i] = (need_old && !(single && h))
+                     ? *(const f32x4*)(Mr + (row_a0 + lr) * ld + col0 + lcl)
+                     : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int e = (tid + (g0 + i) * NT) * 4;
+        const int tr = e / BN, lc = e % BN;
+        const int h = lc / BM, lcl = lc % BM;
+        if (single && h) continue;
+        const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
+        const bool diag = h == 0 && diag0;
+        const f32x4 x = *(const f32x4*)(T + tr * PT + lc);
+        const int64_t grow = row_a0 + lr, gcol = (h ? row_b1 : row_b0) + lcl;
+        const f32x4 so = sov[i];
+        f32x4 sn;
+        uint16_t hh[4], ll[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          sn[q] = sig > 0 ? x[q] : 2.0f * so[q] - x[q];
+          const int c = lcl + q;
+          const double w = diag ? (lr < c ? 2.0 : (lr == c ? 1.0 : 0.0)) : 2.0;
+          const double d = (double)so[q] - (double)x[q];
+          if (diff) pf += w * d * d;
+          if (w > 0.0) pm = fmaxf(pm, fabsf(sn[q]));
+          split_one<T16>(sn[q], esplit, S::kShift, hh + q, ll + q);
+        }
+        if (!upd) continue;
+        *(f32x4*)(T + tr * PT + lc) = sn;      // for the mirror pass
+        const int64_t pi = panel_index(grow, gcol, pdim);   // four columns, one panel row
+        if (!diag || lr < lcl) {
+          *(f32x4*)(Mw + grow * ld + gcol) = sn;
+          *(U4*)(Hw + pi) = U4{hh[0], hh[1], hh[2], hh[3]};
+          *(U4*)(Lw + pi) = U4{ll[0], ll[1], ll[2], ll[3]};
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (lr <= lcl + q) {
+              Mw[grow * ld + gcol + q] = sn[q];
+              Hw[pi + q] = hh[q];
+              Lw[pi + q] = ll[q];
+            }
+        }
+      }
+    }
+    lds_barrier();
+    // mirror block: row lc of the mirror gets T rows 4 qd .. 4 qd + 3 of column lc
+    if (upd) {
+      for (int e = tid; e < BN * (SR / 4); e += NT) {
+        const int qd = e % (SR / 4), lc = e / (SR / 4);
+        const int h = lc / BM, lcl = lc % BM;
+        if (single && h) continue;
+        const bool diag = h == 0 && diag0;
+        const int tr = 4 * qd;
+        const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
+        if (diag && lr >= lcl) continue;       // lr + q < lcl for some q needs lr < lcl
+        f32x4 v;
+        uint16_t hh[4], ll[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          v[q] = T[(tr + q) * PT + lc];
+          split_one<T16>(v[q], esplit, S::kShift, hh + q, ll + q);
+        }
+        const int64_t grow = (h ? row_b1 : row_b0) + lcl, gcol = row_a0 + lr;
+        const int64_t pi = panel_index(grow, gcol, pdim);
+        if (!diag || lr + 3 < lcl) {
+          *(f32x4*)(Mw + grow * ld + gcol) = v;
+          *(U4*)(Hw + pi) = U4{hh[0], hh[1], hh[2], hh[3]};
+          *(U4*)(Lw + pi) = U4{ll[0], ll[1], ll[2], ll[3]};
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (lr + q < lcl) {
+              Mw[grow * ld + gcol + q] = v[q];
+              Hw[pi + q] = hh[q];
+              Lw[pi + q] = ll[q];
+            }
+        }
+      }
+      lds_barrier();
+    }
+  }
+  // workgroup partials in a fixed order: butterfly within each wave, then the
+  // waves in index order
+  __shared__ double red_f[WGM * WGN];
+  __shared__ float red_m[WGM * WGN];
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    pf += __shfl_xor(pf, o);
+    pm = fmaxf(pm, __shfl_xor(pm, o));
+  }
+  if (lane == 0) {
+    red_f[wave] = pf;
+    red_m[wave] = pm;
+  }
+  lds_barrier();
+  if (tid == 0) {
+    double f = 0.0;
+    float mx = 0.0f;
+#pragma unroll
+    for (int w = 0; w < WGM * WGN; ++w) {
+      f += red_f[w];
+      mx = fmaxf(mx, red_m[w]);
+    }
+    a.part_f[a.slot_base + id] = f;
+    a.part_m[a.slot_base + id] = (double)mx;
+  }
+  }  // items
+}
+
 // ------------------------------------------------------------------ direct forms
 template <typename T> struct Direct;
 // Output element r of lane l sits in column l % 16 and in row
@@ -850,6 +1279,21 @@ static hipError_t launch_split_small(const ProductArgs& a, hipStream_t s) {
   constexpr size_t lds = (size_t)2 * (4 * 128) * (kPanelK / 8) * 16;
   return launch_one(k_products_split<T16, 128, kPanelK, 2, 2, 2, 2, true>, 4 * kWave, lds, 2, a,
                     s);
+}
+
+template <typename T16>
+static hipError_t launch_split_pair(const ProductArgs& a, hipStream_t s) {
+  // 128 x 256 items, 8 waves of 64 x 64, three stages, one workgroup per CU
+  constexpr size_t lds = (size_t)3 * (6 * 128) * (kPanelK / 8) * 16;
+  static_assert(lds <= 160 * 1024 - 256, "LDS of one CU");
+  return launch_one(k_products_pair<T16, 2>, 8 * kWave, lds, 1, a, s);
+}
+
+hipError_t launch_products_pair(dmpt_precision prec, const ProductArgs& a, hipStream_t s) {
+  if (!a.probs || !a.part_f || !a.part_m) return hipErrorInvalidValue;
+  if (prec == DMPT_SPLIT_FP16) return launch_split_pair<_Float16>(a, s);
+  if (prec == DMPT_SPLIT_BF16) return launch_split_pair<__bf16>(a, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_products_fused(dmpt_precision prec, int tile, const ProductArgs& a,

@@ -136,15 +136,15 @@ def test_batch_full_equals_single_solves(dm, full_batch):
 
 
 def test_batch_ragged_sizes(dm):
-    """Sizes that are not multiples of 16 or 32 (partial 128-row tiles, the k
-    range rounded up to 32 inside a 256-padded panel layout), 1-3
+    """Sizes that are not multiples of 16 or 32, down to 2 (partial 128-row
+    tiles, the k range rounded up to 32 inside a 256-padded panel layout), 1-3
     perturbations, against the oracle and against the same problems solved
     alone (equal bitwise: only exact zeros differ in the k range)."""
     from oracle import exact
     from workloads import dense_gapped_problem
-    sizes = [37, 100, 129, 257, 300, 511, 513]
-    probs = [dense_gapped_problem(n, n // 2 + (i % 3) - 1, 0.6, 900 + n, h1="diag",
-                                  k=1 + i % 3) for i, n in enumerate(sizes)]
+    sizes = [2, 3, 17, 37, 100, 129, 257, 300, 511, 513]
+    probs = [dense_gapped_problem(n, min(n - 1, max(1, n // 2 + (i % 3) - 1)), 0.6, 900 + n,
+                                  h1="diag", k=1 + i % 3) for i, n in enumerate(sizes)]
     (res,), info = _run(dm, probs)
     P0, P1, st, _ = res
     for i, p in enumerate(probs):

@@ -294,7 +294,7 @@ def test_persistent_loop_model(dm, N, k, k_max):
                                        (4096, 1, 8)])
 def test_persistent_loop_model_128(dm, N, k, k_max):
     """The same walk for the 128-row fused launch that small single-problem
-    contexts (and the batch) use: 2 x 2 waves of 64 x 64, 32 KB stages, two
+    contexts use: 2 x 2 waves of 64 x 64, 32 KB stages, two
     workgroups per CU (grid 512), tiles of 128 rows inside the 256-row panel
     blocks, the k loop over N rounded up to 32, partial slots sized for the
     128-row tiling."""
@@ -338,3 +338,122 @@ def test_persistent_loop_model_128(dm, N, k, k_max):
     # epilogue staging of the 128-row tile inside the launch's 2 x 32 KB
     sr, pt = 64, bm + 4
     assert sr * pt * 4 <= 2 * stage * 16
+
+
+# ---------------------------------------------------------------------------
+# Host model of the batch's pair launch (k_products_pair): items of two
+# 128 x 128 tiles (ti, tj), (ti, tj2) of one row band, 2 x 4 waves of 64 x 64,
+# six load arrays of 128 rows (A_hi, A_lo, B0_hi, B0_lo, B1_hi, B1_lo) per
+# 48 KB stage, three stages (k-tile t in stage t % 3), one workgroup per CU.
+P_BM, P_NT, P_CH, P_NARR, P_STAGES = 128, 512, 4, 6, 3
+P_STAGE = P_NARR * P_BM * P_CH                 # chunks per stage
+P_RPW, P_RPL = 64 // P_CH, P_NT // P_CH
+P_WGM, P_WGN, P_WT = 2, 4, 64
+
+
+def pair_items(T, k):
+    """(out, ti, tj, tj2) as the batch builds them: responses, then X; per row
+    band the tiles from the diagonal two by two, an odd last one alone."""
+    v = []
+    for out in list(range(1, k + 1)) + [0]:
+        for ti in range(T):
+            for tj in range(ti, T, 2):
+                v.append((out, ti, tj, tj + 1 if tj + 1 < T else -1))
+    return v
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 7, 8, 9])
+def test_pair_items_cover_every_tile_once(T):
+    for k in (1, 3):
+        seen = {}
+        for out, ti, tj, tj2 in pair_items(T, k):
+            assert 0 <= ti <= tj < T and (tj2 < 0 or tj < tj2 < T)
+            for c in (tj, tj2):
+                if c >= 0:
+                    seen[(out, ti, c)] = seen.get((out, ti, c), 0) + 1
+        want = {(o, i, j) for o in range(k + 1) for i in range(T) for j in range(i, T)}
+        assert set(seen) == want and all(n == 1 for n in seen.values())
+
+
+def test_pair_launch_lds_layout():
+    # LDS: three stages plus the kernel's static partial arrays within one CU
+    assert P_STAGES * P_STAGE * 16 + 8 * 8 + 8 * 4 <= 160 * 1024
+    tid = np.arange(P_NT)
+    lane, wave = tid % 64, tid // 64
+    lrow, lsl = tid // P_CH, tid % P_CH
+    csrc = lsl ^ ((lrow >> 2) & (P_CH - 1))
+    voff = lrow * 32 + csrc * 8
+    assert voff.min() >= 0 and voff.max() + 8 <= 256 * 32 and lrow.max() < P_BM
+    held = {}
+    for i in range(P_NARR):
+        dst = (i * P_RPL + wave * P_RPW) * P_CH + lane
+        for d, r, c in zip(dst, i * P_RPL + lrow, csrc):
+            assert int(d) not in held
+            held[int(d)] = (int(r), int(c))
+    assert sorted(held) == list(range(P_STAGE))
+    # fragment reads of every wave: A from arrays 0/1, B from 2/3 (left) or 4/5 (right)
+    for wm in range(P_WGM):
+        for wn in range(P_WGN):
+            half = wn >> 1
+            for g in range(8):
+                a_side = g < 4
+                idx = g % 2 if a_side else (g - 4) % 2
+                lo = (g >= 2) if a_side else (g >= 6)
+                R = (((P_BM if lo else 0) + wm * P_WT + idx * 32 + np.arange(64) % 32) if a_side
+                     else ((2 + 2 * half + (1 if lo else 0)) * P_BM + (wn & 1) * P_WT + idx * 32
+                           + np.arange(64) % 32))
+                arr = R // P_BM
+                assert np.all(arr == ((1 if lo else 0) if a_side else 2 + 2 * half + (1 if lo else 0)))
+                for kk in range(2):
+                    c = kk * 2 + np.arange(64) // 32
+                    slot = R * P_CH + (c ^ ((R >> 2) & (P_CH - 1)))
+                    assert slot.max() < P_STAGE
+                    for s_, r_, c_ in zip(slot, R, c):
+                        assert held[int(s_)] == (int(r_), int(c_))
+    # epilogue staging: 64 rows of 256 + 4 floats inside the three stages
+    SR, PT, BN = 64, 260, 256
+    assert SR * PT * 4 <= P_STAGES * P_STAGE * 16
+    ITER = SR * BN // (4 * P_NT)
+    for m in range(2):
+        cov = []
+        for g in range(ITER):
+            e = (tid + g * P_NT) * 4
+            tr, lc = e // BN, e % BN
+            assert np.array_equal(lc, (tid * 4) % BN)        # a thread keeps its column
+            lr = (tr >> 5) * P_WT + m * 32 + (tr & 31)
+            assert tr.max() < SR and lr.max() < P_BM and lc.max() + 3 < BN
+            cov.append(lr * BN + lc)
+        cov = np.concatenate(cov)
+        assert len(np.unique(cov)) == len(cov) == SR * BN // 4
+        e = np.arange(BN * (SR // 4))
+        qd, lc = e % (SR // 4), e // (SR // 4)
+        lr = ((4 * qd) >> 5) * P_WT + m * 32 + ((4 * qd) & 31)
+        assert lc.max() < BN and np.all(lr % 4 == 0) and lr.max() + 3 < P_BM
+
+
+@pytest.mark.parametrize("N,k", [(37, 1), (100, 2), (129, 3), (300, 2), (513, 1), (1024, 3)])
+def test_pair_launch_fetches_and_stores_in_bounds(N, k):
+    """Per item: the six panel-block offsets of the first and last k-tile of
+    each product, and the epilogue's extreme master and panel addresses of
+    both tiles and their mirrors, inside the problem's buffers (panel layout
+    padded to 256, masters of row stride Np, k loop over N rounded to 32)."""
+    Np = -(-N // 256) * 256
+    T, ld = -(-N // P_BM), Np
+    kblocks, kt_per = Np // 32, -(-N // 32)
+    assert kt_per <= kblocks and T * P_BM <= Np
+    blk = 256 * 32
+    for out, ti, tj, tj2 in pair_items(T, k):
+        nprod = 1 if out == 0 else 2
+        rows = [ti * P_BM, tj * P_BM, (tj2 if tj2 >= 0 else tj) * P_BM]
+        for t in (0, nprod * kt_per - 1):
+            p = int(t >= kt_per)
+            kofs = (t - p * kt_per) * blk
+            for r0 in rows:
+                off = (r0 // 256) * kblocks * blk + (r0 % 256) * 32
+                assert (r0 % 256) + P_BM <= 256             # a tile stays in one panel block
+                assert off + kofs >= 0 and off + kofs + (P_BM - 1) * 32 + 32 <= Np * Np
+        for c0 in rows[1:]:
+            for grow, gcol in ((ti * P_BM + P_BM - 1, c0 + P_BM - 4), (c0 + P_BM - 1, ti * P_BM + P_BM - 4)):
+                assert grow * ld + gcol + 4 <= Np * ld
+                pi = ((grow // 256) * kblocks + gcol // 32) * blk + (grow % 256) * 32 + gcol % 32
+                assert gcol % 32 + 4 <= 32 and pi + 4 <= Np * Np

@@ -297,21 +297,34 @@ std::vector<TileItem> triangle_items(int T, int k, int prob) {
   return v;
 }
 
-// Items of the pair launch: the tiles (ti, tj), tj >= ti, of each row band
-// two by two from the diagonal, an odd last one alone (tj2 = -1).
+// Items of the pair launch.  Per output, the tiles (ti, tj), tj >= ti, of
+// each row band two by two from the diagonal (they share the A panels); a
+// band with an odd count leaves its last tile (ti, T - 1), and these, all in
+// the last column band, pair up two by two (sharing the B panels), the odd
+// one out alone (ti2 = -1).
 std::vector<TileItem> pair_items(int T, int k, int prob) {
   std::vector<TileItem> v;
+  auto add = [&](int out, int ti, int tj, int ti2, int tj2) {
+    TileItem it;
+    it.out = (int16_t)out;
+    it.prob = (int16_t)prob;
+    it.ti = ti;
+    it.tj = tj;
+    it.ti2 = ti2;
+    it.tj2 = tj2;
+    v.push_back(it);
+  };
   auto add_out = [&](int out) {
-    for (int ti = 0; ti < T; ++ti)
-      for (int tj = ti; tj < T; tj += 2) {
-        TileItem it;
-        it.out = (int16_t)out;
-        it.prob = (int16_t)prob;
-        it.ti = ti;
-        it.tj = tj;
-        it.tj2 = tj + 1 < T ? tj + 1 : -1;
-        v.push_back(it);
-      }
+    std::vector<int> rest;
+    for (int ti = 0; ti < T; ++ti) {
+      int tj = ti;
+      for (; tj + 1 < T; tj += 2) add(out, ti, tj, ti, tj + 1);
+      if (tj < T) rest.push_back(ti);
+    }
+    for (size_t i = 0; i < rest.size(); i += 2) {
+      if (i + 1 < rest.size()) add(out, rest[i], T - 1, rest[i + 1], T - 1);
+      else add(out, rest[i], T - 1, -1, -1);
+    }
   };
   for (int j = 0; j < k; ++j) add_out(1 + j);
   add_out(0);

@@ -88,7 +88,8 @@ struct TileItem {
   int16_t out;               // 0: X, 1 + j: response j; < 0: placeholder, skipped
   int16_t prob;              // problem index (batched launches; 0 otherwise)
   int32_t ti, tj;            // tile row/col (ti <= tj)
-  int32_t tj2 = -1;          // pair launches: second tile (ti, tj2), tj < tj2; < 0: none
+  int32_t ti2 = -1, tj2 = -1;   // pair launches: second tile (ti2, tj2), sharing a row band
+                                // (ti2 == ti) or a column band (tj2 == tj); ti2 < 0: none
 };
 
 constexpr int kMaxKB = 3;    // most responses per problem of a batch
@@ -173,8 +174,8 @@ void product_items(int T, int mode, TileItem* out);   // T (T + 1) / 2 or T * T 
 // state, decided before the launch.
 hipError_t launch_products_fused(dmpt_precision prec, int tile, const ProductArgs& a,
                                  hipStream_t s);
-// The same on items of two 128 x 128 tiles of one row band (TileItem::tj2),
-// one workgroup per CU: the batch's small-tile class.
+// The same on items of two 128 x 128 tiles that share a row or a column band
+// (TileItem::ti2, tj2), one workgroup per CU: the batch's small-tile class.
 hipError_t launch_products_pair(dmpt_precision prec, const ProductArgs& a, hipStream_t s);
 // N_X = Tr X_n of the coming fused products, before them: the diagonal 32 x 32
 // fragments of X_n = S_{n-1}^2, one wave each, with the product kernel's MFMA

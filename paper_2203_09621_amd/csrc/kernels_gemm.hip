@@ -550,17 +550,28 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
-// Fused layer products on items of two 128 x 128 tiles of one row band,
-// (ti, tj) and (ti, tj2): both read the A panels of band ti (rows of S, or of
-// S1_j for the second product of a response), so one k-tile loads A once for
-// both, 48 KB for 96 MFMAs per wave pair instead of 64 KB.  Eight waves of
-// 64 x 64 (waves with wn < 2 hold tile (ti, tj), the others (ti, tj2)), one
+// Memory that no kernel writes while the product launch runs (the items, the
+// problem descriptors, the layer states, which the decision kernels write
+// between launches), read through the constant address space: workgroup-
+// uniform reads then become scalar loads, which do not queue behind the
+// vector loads in flight and are not counted with them.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cst(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
+// Fused layer products on items of two 128 x 128 tiles that share a band:
+// (ti, tj) and (ti, tj2) read the same A panels (rows of S, or of S1_j for the
+// second product of a response), (ti, tj) and (ti2, tj) the same B panels.
+// One k-tile then loads the shared panels once for both tiles, 48 KB for 96
+// MFMAs per wave pair instead of 64 KB.  Eight waves of 64 x 64 (waves with
+// wn < 2 hold tile (ti, tj), the others the second tile), one
 // workgroup per CU and three LDS stages, so the loads of k-tile t + 3 go out
 // while tile t is multiplied and are waited for two tiles later: the batch's
 // small problems miss the L2 often, and one tile of lead time does not cover
 // that latency.  No barrier waits for global stores or for loads beyond the
-// one the pipeline needs (lds_barrier).  A band with an odd number of tiles
-// leaves one single tile (tj2 < 0): its second B panel repeats the first and
+// one the pipeline needs (lds_barrier).  A tile without a partner (ti2 < 0)
+// loads its panels as a row pair whose second B panel repeats the first, and
 // the waves of the right half only load and wait.  First-order items only
 // (X and X1_j).
 template <typename T16, int SWZ>
@@ -572,7 +583,8 @@ k_products_pair(const ProductArgs a) {
   constexpr int NT = WGM * WGN * kWave;
   constexpr int WTM = 64, WTN = 64, FM = WTM / 32, FN = WTN / 32;
   constexpr int CH = BK / 8;                 // 16-byte chunks per row of a k-tile
-  constexpr int NARR = 6;                    // A_hi | A_lo | B0_hi | B0_lo | B1_hi | B1_lo
+  constexpr int NARR = 6;                    // X_hi | X_lo | Y0_hi | Y0_lo | Y1_hi | Y1_lo
+                                             // X: the shared panel, Y_h: tile h's other one
   constexpr int STAGE = NARR * BM * CH;      // chunks per pipeline stage
   constexpr int RPW = kWave / CH;            // rows one wave fills per load instruction
   constexpr int RPL = NT / CH;               // rows all waves fill per load round
@@ -603,20 +615,31 @@ k_products_pair(const ProductArgs a) {
   // the contiguous block I * kblocks + kt of kPanelRows x kPanelK elements).
   struct Ops {
     TileItem it;
-    int sexp, kt_per, ktiles;
+    int sexp, kt_per, ktiles, colp;            // colp: the tiles share their B panels
     const uint16_t* q[4];                      // hi_S, lo_S, hi_T, lo_T (T = S1_j or S)
-    int64_t offa, offb0, offb1;
+    int64_t offx, offy0, offy1;
   };
   // The first item at or after position id (stepping by the grid) with work
   // to do; false if there is none.
   auto find = [&](int& id, Ops& o) -> bool {
     for (; id < a.n_items; id += gridDim.x) {
-      o.it = a.items[id];
-      o.sexp = 0;
-      if (!item_active<true>(a, o.it, &o.sexp)) continue;
-      const ProblemDesc* pd = a.probs + o.it.prob;
-      const LayerState* fst = pd->state;
+      // the item as five words (out | prob << 16, ti, tj, ti2, tj2)
+      const auto* w = cst((const uint32_t*)(a.items + id));
+      const uint32_t w0 = w[0];
+      o.it.out = (int16_t)(w0 & 0xffffu);
+      o.it.prob = (int16_t)(w0 >> 16);
+      o.it.ti = (int32_t)w[1];
+      o.it.tj = (int32_t)w[2];
+      o.it.ti2 = (int32_t)w[3];
+      o.it.tj2 = (int32_t)w[4];
+      if (o.it.out < 0) continue;               // placeholder of a balanced round
+      const auto* pd = cst(a.probs + o.it.prob);
+      const auto* fst = cst(pd->state);
       const int j = o.it.out - 1;
+      // skip flags as in item_active (fused launch)
+      if (fst->done) continue;
+      if (o.it.out == 0 ? (fst->d0 && !fst->d0_now) : fst->d1[j] != 0) continue;
+      o.sexp = o.it.out == 0 ? 0 : fst->s1_exp_split[j];
       const int sp = fst->s_par;
       const int lp = (fst->n - 1) & 1;         // S1_{n-1} split
       const uint16_t* sh = (const uint16_t*)pd->s_hi[sp];
@@ -628,10 +651,12 @@ k_products_pair(const ProductArgs a) {
       auto block_of = [&](int64_t r0) {
         return uni((r0 / kPanelRows) * kblocks * (kPanelRows * kPanelK) + (r0 % kPanelRows) * kPanelK);
       };
-      const int tj2 = uni(o.it.tj2);
-      o.offa = block_of((int64_t)o.it.ti * BM);
-      o.offb0 = block_of((int64_t)o.it.tj * BM);
-      o.offb1 = block_of((int64_t)(tj2 < 0 ? o.it.tj : tj2) * BM);
+      const int ti = uni(o.it.ti), tj = uni(o.it.tj);
+      const int ti2 = uni(o.it.ti2), tj2 = uni(o.it.tj2);
+      o.colp = ti2 >= 0 && ti2 != ti;
+      o.offx = block_of((int64_t)(o.colp ? tj : ti) * BM);
+      o.offy0 = block_of((int64_t)(o.colp ? ti : tj) * BM);
+      o.offy1 = block_of((int64_t)(ti2 < 0 ? tj : (o.colp ? ti2 : tj2)) * BM);
       o.kt_per = uni((int)(pd->kdim / BK));
       o.ktiles = uni((o.it.out == 0 ? 1 : 2) * o.kt_per);
       return true;
@@ -645,18 +670,19 @@ k_products_pair(const ProductArgs a) {
   // stay there unless read out here once per item.
   struct Plan {
     const uint16_t* q[4];
-    int64_t offa, offb0, offb1;
-    int kt_per, ktiles;
+    int64_t offx, offy0, offy1;
+    int kt_per, ktiles, colp;
   };
   auto plan_of = [&](const Ops& o) {
     Plan pl;
 #pragma unroll
     for (int r = 0; r < 4; ++r) pl.q[r] = uni(o.q[r]);
-    pl.offa = uni(o.offa);
-    pl.offb0 = uni(o.offb0);
-    pl.offb1 = uni(o.offb1);
+    pl.offx = uni(o.offx);
+    pl.offy0 = uni(o.offy0);
+    pl.offy1 = uni(o.offy1);
     pl.kt_per = uni(o.kt_per);
     pl.ktiles = uni(o.ktiles);
+    pl.colp = uni(o.colp);
     return pl;
   };
   struct Fetch { const uint16_t* q[NARR]; u32x4* dst; };
@@ -669,12 +695,16 @@ k_products_pair(const ProductArgs a) {
     const uint16_t* al = p ? o.q[3] : o.q[1];
     const uint16_t* bh = p ? o.q[0] : o.q[2];
     const uint16_t* bl = p ? o.q[1] : o.q[3];
-    f.q[0] = ah + o.offa + kofs;
-    f.q[1] = al + o.offa + kofs;
-    f.q[2] = bh + o.offb0 + kofs;
-    f.q[3] = bl + o.offb0 + kofs;
-    f.q[4] = bh + o.offb1 + kofs;
-    f.q[5] = bl + o.offb1 + kofs;
+    const uint16_t* xh = o.colp ? bh : ah;
+    const uint16_t* xl = o.colp ? bl : al;
+    const uint16_t* yh = o.colp ? ah : bh;
+    const uint16_t* yl = o.colp ? al : bl;
+    f.q[0] = xh + o.offx + kofs;
+    f.q[1] = xl + o.offx + kofs;
+    f.q[2] = yh + o.offy0 + kofs;
+    f.q[3] = yl + o.offy0 + kofs;
+    f.q[4] = yh + o.offy1 + kofs;
+    f.q[5] = yl + o.offy1 + kofs;
     f.dst = lds + (t0 % STAGES) * STAGE;
     return f;
   };
@@ -694,16 +724,19 @@ k_products_pair(const ProductArgs a) {
   constexpr int NM = 3 * FM * FN;
   static_assert(NM >= NF, "at least one MFMA per LDS read");
   struct Frag { V ah[FM], al[FM], bh[FN], bl[FN]; };
+  // first LDS row of the A and of the B panels of this wave's tile (hi; lo
+  // follows BM rows later), set per item: the shared panel sits in arrays 0-1
+  int rowA = 0, rowB = 0;
   auto read_one = [&](int stage, int kk, Frag& f, int g) {
     const u32x4* base = lds + stage * STAGE;
     const int c = kk * 2 + (lane >> 5);
     const bool a_side = g < 2 * FM;
     const int idx = a_side ? g % FM : (g - 2 * FM) % FN;
     const bool lo = a_side ? g >= FM : g >= 2 * FM + FN;
-    const int R = a_side ? (lo ? BM : 0) + wm * WTM + idx * 32 + (lane & 31)
-                         : (2 + 2 * half + (lo ? 1 : 0)) * BM + (wn & 1) * WTN + idx * 32 +
-                               (lane & 31);
-    const int cc = c ^ ((R >> SWZ) & (CH - 1));
+    const int rin = (a_side ? wm * WTM : (wn & 1) * WTN) + idx * 32 + (lane & 31);
+    // the array offsets are multiples of BM rows, which the swizzle ignores
+    const int cc = c ^ ((rin >> SWZ) & (CH - 1));
+    const int R = (a_side ? rowA : rowB) + (lo ? BM : 0) + rin;
     const V v = __builtin_bit_cast(V, base[R * CH + cc]);
     if (a_side) {
       if (lo) f.al[idx] = v; else f.ah[idx] = v;
@@ -724,14 +757,18 @@ k_products_pair(const ProductArgs a) {
   const Plan pl = plan_of(cur);
   const TileItem it = cur.it;
   const int j = it.out - 1;
-  const ProblemDesc* pd = a.probs + it.prob;
-  const LayerState* fst = pd->state;
+  const auto* pd = cst(a.probs + it.prob);
+  const auto* fst = cst(pd->state);
   const int64_t ld = pd->ld, pdim = pd->pdim;
-  const int tj2 = uni(it.tj2);
-  const bool single = tj2 < 0;
+  const int ti2 = uni(it.ti2), tj2 = uni(it.tj2);
+  const bool single = ti2 < 0;
   const bool live = !(single && half);       // wave-uniform
-  const int64_t row_a0 = (int64_t)it.ti * BM, row_b0 = (int64_t)it.tj * BM;
-  const int64_t row_b1 = single ? row_b0 : (int64_t)tj2 * BM;
+  rowA = pl.colp ? (2 + 2 * half) * BM : 0;
+  rowB = pl.colp ? 0 : (2 + 2 * half) * BM;
+  // origin of tile h: rows r0_h, columns c0_h
+  const int64_t r0_0 = (int64_t)uni(it.ti) * BM, c0_0 = (int64_t)uni(it.tj) * BM;
+  const int64_t r0_1 = single ? r0_0 : (int64_t)ti2 * BM;
+  const int64_t c0_1 = single ? c0_0 : (int64_t)tj2 * BM;
   const int ktiles = pl.ktiles;
 
   f32x16 acc[FM][FN];
@@ -809,11 +846,10 @@ k_products_pair(const ProductArgs a) {
   __builtin_amdgcn_s_waitcnt(0);
   lds_barrier();
 
-  // Fused epilogue, as in k_products_split, over the 256 columns of the pair:
-  // column lc of the staged rows is column lc % 128 of tile (ti, tj) (lc < 128)
-  // or of tile (ti, tj2).  Only tile (ti, tj) can lie on the diagonal.
+  // Fused epilogue, as in k_products_split, over the 256 staged columns of the
+  // pair: column lc is column lc % 128 of tile lc / 128 (at r0_h, c0_h).
   const float scale = ldexpf(1.0f, -(S::kShift + cur.sexp));
-  const bool diag0 = it.ti == it.tj;
+  const bool diag0 = r0_0 == c0_0, diag1 = r0_1 == c0_1;
   constexpr int ITER = SR * BN / (4 * NT);   // float4 groups per thread and round
   constexpr int G = ITER < 4 ? ITER : 4;
   static_assert(SR * BN % (4 * NT) == 0 && ITER % G == 0, "whole float4 groups per thread");
@@ -855,9 +891,9 @@ k_products_pair(const ProductArgs a) {
         const int tr = e / BN, lc = e % BN;
         const int h = lc / BM, lcl = lc % BM;
         const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
-        const int64_t col0 = h ? row_b1 : row_b0;
+        const int64_t rb = h ? r0_1 : r0_0, cb = h ? c0_1 : c0_0;
         sov[i] = (need_old && !(single && h))
-                     ? *(const f32x4*)(Mr + (row_a0 + lr) * ld + col0 + lcl)
+                     ? *(const f32x4*)(Mr + (rb + lr) * ld + cb + lcl)
                      : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
       }
 #pragma unroll
@@ -867,9 +903,9 @@ k_products_pair(const ProductArgs a) {
         const int h = lc / BM, lcl = lc % BM;
         if (single && h) continue;
         const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
-        const bool diag = h == 0 && diag0;
+        const bool diag = h ? diag1 : diag0;
         const f32x4 x = *(const f32x4*)(T + tr * PT + lc);
-        const int64_t grow = row_a0 + lr, gcol = (h ? row_b1 : row_b0) + lcl;
+        const int64_t grow = (h ? r0_1 : r0_0) + lr, gcol = (h ? c0_1 : c0_0) + lcl;
         const f32x4 so = sov[i];
         f32x4 sn;
         uint16_t hh[4], ll[4];
@@ -908,7 +944,7 @@ k_products_pair(const ProductArgs a) {
         const int qd = e % (SR / 4), lc = e / (SR / 4);
         const int h = lc / BM, lcl = lc % BM;
         if (single && h) continue;
-        const bool diag = h == 0 && diag0;
+        const bool diag = h ? diag1 : diag0;
         const int tr = 4 * qd;
         const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
         if (diag && lr >= lcl) continue;       // lr + q < lcl for some q needs lr < lcl
@@ -919,7 +955,7 @@ k_products_pair(const ProductArgs a) {
           v[q] = T[(tr + q) * PT + lc];
           split_one<T16>(v[q], esplit, S::kShift, hh + q, ll + q);
         }
-        const int64_t grow = (h ? row_b1 : row_b0) + lcl, gcol = row_a0 + lr;
+        const int64_t grow = (h ? c0_1 : c0_0) + lcl, gcol = (h ? r0_1 : r0_0) + lr;
         const int64_t pi = panel_index(grow, gcol, pdim);
         if (!diag || lr + 3 < lcl) {
           *(f32x4*)(Mw + grow * ld + gcol) = v;

@@ -342,9 +342,11 @@ def test_persistent_loop_model_128(dm, N, k, k_max):
 
 # ---------------------------------------------------------------------------
 # Host model of the batch's pair launch (k_products_pair): items of two
-# 128 x 128 tiles (ti, tj), (ti, tj2) of one row band, 2 x 4 waves of 64 x 64,
-# six load arrays of 128 rows (A_hi, A_lo, B0_hi, B0_lo, B1_hi, B1_lo) per
-# 48 KB stage, three stages (k-tile t in stage t % 3), one workgroup per CU.
+# 128 x 128 tiles that share a row band (ti2 == ti: the A panels) or a column
+# band (tj2 == tj: the B panels), 2 x 4 waves of 64 x 64, six load arrays of
+# 128 rows (X_hi, X_lo: the shared panel; Y0_hi, Y0_lo, Y1_hi, Y1_lo: each
+# tile's other panel) per 48 KB stage, three stages (k-tile t in stage t % 3),
+# one workgroup per CU.
 P_BM, P_NT, P_CH, P_NARR, P_STAGES = 128, 512, 4, 6, 3
 P_STAGE = P_NARR * P_BM * P_CH                 # chunks per stage
 P_RPW, P_RPL = 64 // P_CH, P_NT // P_CH
@@ -352,27 +354,68 @@ P_WGM, P_WGN, P_WT = 2, 4, 64
 
 
 def pair_items(T, k):
-    """(out, ti, tj, tj2) as the batch builds them: responses, then X; per row
-    band the tiles from the diagonal two by two, an odd last one alone."""
+    """(out, ti, tj, ti2, tj2) as the batch builds them: responses, then X;
+    per row band the tiles from the diagonal two by two, the odd last ones
+    (all in column band T - 1) two by two, a last odd one alone."""
     v = []
     for out in list(range(1, k + 1)) + [0]:
+        rest = []
         for ti in range(T):
-            for tj in range(ti, T, 2):
-                v.append((out, ti, tj, tj + 1 if tj + 1 < T else -1))
+            tj = ti
+            while tj + 1 < T:
+                v.append((out, ti, tj, ti, tj + 1))
+                tj += 2
+            if tj < T:
+                rest.append(ti)
+        for i in range(0, len(rest), 2):
+            if i + 1 < len(rest):
+                v.append((out, rest[i], T - 1, rest[i + 1], T - 1))
+            else:
+                v.append((out, rest[i], T - 1, -1, -1))
     return v
 
 
-@pytest.mark.parametrize("T", [1, 2, 3, 4, 7, 8, 9])
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 7, 8, 9])
 def test_pair_items_cover_every_tile_once(T):
     for k in (1, 3):
         seen = {}
-        for out, ti, tj, tj2 in pair_items(T, k):
-            assert 0 <= ti <= tj < T and (tj2 < 0 or tj < tj2 < T)
-            for c in (tj, tj2):
-                if c >= 0:
-                    seen[(out, ti, c)] = seen.get((out, ti, c), 0) + 1
+        alone = 0
+        for out, ti, tj, ti2, tj2 in pair_items(T, k):
+            assert 0 <= ti <= tj < T
+            if ti2 < 0:
+                assert tj2 < 0
+                alone += 1
+            else:
+                assert ti2 <= tj2 < T and (ti2 == ti) != (tj2 == tj)   # one shared band
+            for t in ((ti, tj), (ti2, tj2)):
+                if t[0] >= 0:
+                    seen[(out,) + t] = seen.get((out,) + t, 0) + 1
         want = {(o, i, j) for o in range(k + 1) for i in range(T) for j in range(i, T)}
         assert set(seen) == want and all(n == 1 for n in seen.values())
+        assert alone <= k + 1                           # at most one lone tile per output
+
+
+def _pair_reads(colp):
+    """LDS slot each lane reads for every (wave, fragment, k step)."""
+    out = []
+    for wm in range(P_WGM):
+        for wn in range(P_WGN):
+            half = wn >> 1
+            row_a = (2 + 2 * half) * P_BM if colp else 0
+            row_b = 0 if colp else (2 + 2 * half) * P_BM
+            for g in range(8):
+                a_side = g < 4
+                idx = g % 2 if a_side else (g - 4) % 2
+                lo = (g >= 2) if a_side else (g >= 6)
+                rin = (wm * P_WT if a_side else (wn & 1) * P_WT) + idx * 32 + np.arange(64) % 32
+                R = (row_a if a_side else row_b) + (P_BM if lo else 0) + rin
+                want_arr = ((1 if lo else 0) if a_side != colp else 2 + 2 * half + (1 if lo else 0))
+                assert np.all(R // P_BM == want_arr) and np.all(R % P_BM == rin)
+                for kk in range(2):
+                    c = kk * 2 + np.arange(64) // 32
+                    slot = R * P_CH + (c ^ ((rin >> 2) & (P_CH - 1)))
+                    out.append((R, c, slot))
+    return out
 
 
 def test_pair_launch_lds_layout():
@@ -391,25 +434,13 @@ def test_pair_launch_lds_layout():
             assert int(d) not in held
             held[int(d)] = (int(r), int(c))
     assert sorted(held) == list(range(P_STAGE))
-    # fragment reads of every wave: A from arrays 0/1, B from 2/3 (left) or 4/5 (right)
-    for wm in range(P_WGM):
-        for wn in range(P_WGN):
-            half = wn >> 1
-            for g in range(8):
-                a_side = g < 4
-                idx = g % 2 if a_side else (g - 4) % 2
-                lo = (g >= 2) if a_side else (g >= 6)
-                R = (((P_BM if lo else 0) + wm * P_WT + idx * 32 + np.arange(64) % 32) if a_side
-                     else ((2 + 2 * half + (1 if lo else 0)) * P_BM + (wn & 1) * P_WT + idx * 32
-                           + np.arange(64) % 32))
-                arr = R // P_BM
-                assert np.all(arr == ((1 if lo else 0) if a_side else 2 + 2 * half + (1 if lo else 0)))
-                for kk in range(2):
-                    c = kk * 2 + np.arange(64) // 32
-                    slot = R * P_CH + (c ^ ((R >> 2) & (P_CH - 1)))
-                    assert slot.max() < P_STAGE
-                    for s_, r_, c_ in zip(slot, R, c):
-                        assert held[int(s_)] == (int(r_), int(c_))
+    # fragment reads, row pairs (A shared) and column pairs (B shared): the
+    # slot a lane reads holds the row and chunk it wants
+    for colp in (False, True):
+        for R, c, slot in _pair_reads(colp):
+            assert slot.max() < P_STAGE
+            for s_, r_, c_ in zip(slot, R, c):
+                assert held[int(s_)] == (int(r_), int(c_))
     # epilogue staging: 64 rows of 256 + 4 floats inside the three stages
     SR, PT, BN = 64, 260, 256
     assert SR * PT * 4 <= P_STAGES * P_STAGE * 16
@@ -431,7 +462,8 @@ def test_pair_launch_lds_layout():
         assert lc.max() < BN and np.all(lr % 4 == 0) and lr.max() + 3 < P_BM
 
 
-@pytest.mark.parametrize("N,k", [(37, 1), (100, 2), (129, 3), (300, 2), (513, 1), (1024, 3)])
+@pytest.mark.parametrize("N,k", [(2, 1), (37, 1), (100, 2), (129, 3), (300, 2), (513, 1),
+                                 (1024, 3)])
 def test_pair_launch_fetches_and_stores_in_bounds(N, k):
     """Per item: the six panel-block offsets of the first and last k-tile of
     each product, and the epilogue's extreme master and panel addresses of
@@ -442,18 +474,24 @@ def test_pair_launch_fetches_and_stores_in_bounds(N, k):
     kblocks, kt_per = Np // 32, -(-N // 32)
     assert kt_per <= kblocks and T * P_BM <= Np
     blk = 256 * 32
-    for out, ti, tj, tj2 in pair_items(T, k):
+    for out, ti, tj, ti2, tj2 in pair_items(T, k):
         nprod = 1 if out == 0 else 2
-        rows = [ti * P_BM, tj * P_BM, (tj2 if tj2 >= 0 else tj) * P_BM]
+        colp = ti2 >= 0 and ti2 != ti
+        x = tj if colp else ti
+        y0 = ti if colp else tj
+        y1 = tj if ti2 < 0 else (ti2 if colp else tj2)
         for t in (0, nprod * kt_per - 1):
             p = int(t >= kt_per)
             kofs = (t - p * kt_per) * blk
-            for r0 in rows:
+            for band in (x, y0, y1):
+                r0 = band * P_BM
                 off = (r0 // 256) * kblocks * blk + (r0 % 256) * 32
                 assert (r0 % 256) + P_BM <= 256             # a tile stays in one panel block
                 assert off + kofs >= 0 and off + kofs + (P_BM - 1) * 32 + 32 <= Np * Np
-        for c0 in rows[1:]:
-            for grow, gcol in ((ti * P_BM + P_BM - 1, c0 + P_BM - 4), (c0 + P_BM - 1, ti * P_BM + P_BM - 4)):
+        tiles = [(ti, tj)] + ([(ti2, tj2)] if ti2 >= 0 else [])
+        for r, c in tiles:
+            for grow, gcol in ((r * P_BM + P_BM - 1, c * P_BM + P_BM - 4),
+                               (c * P_BM + P_BM - 1, r * P_BM + P_BM - 4)):
                 assert grow * ld + gcol + 4 <= Np * ld
                 pi = ((grow // 256) * kblocks + gcol // 32) * blk + (grow % 256) * 32 + gcol % 32
                 assert gcol % 32 + 4 <= 32 and pi + 4 <= Np * Np

@@ -74,6 +74,10 @@ typedef struct {
                               dmpt_adjoint can run; 0 (default): no adjoint workspace */
   int32_t graph;           /* batched solves: nonzero (default) captures the whole response in
                               one HIP graph on first use and replays it */
+  int32_t tile_threshold;  /* batched solves: < 0 (default) times the candidate thresholds at
+                              init and keeps the fastest; >= 0 fixes it: problems whose size
+                              padded to 256 is at most this use 128-row tiles, the others
+                              256-row tiles */
 } dmpt_options;
 
 typedef struct {
@@ -195,7 +199,8 @@ void dmpt_destroy(dmpt_ctx* ctx);
  * sequence and stopping tests and stops on its own.  Split precisions only
  * (DMPT_SPLIT_BF16 / DMPT_SPLIT_FP16).  The tile size of each problem's
  * products (256 or 128 rows) is chosen at init by timing candidate size
- * thresholds on this batch.  With options.graph (default) the whole response
+ * thresholds on this batch, unless options.tile_threshold fixes it.  With
+ * options.graph (default) the whole response
  * (normalisation, every layer up to max_layers, outputs) is one HIP graph,
  * captured on the first dmpt_batch_response and replayed afterwards. */
 typedef struct dmpt_batch dmpt_batch;

@@ -33,7 +33,7 @@ EXPORTS = ["dmpt_default_options", "dmpt_init", "dmpt_set_hamiltonian", "dmpt_re
 class DmptOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_layers", c_int32),
                 ("check_symmetry", c_int32), ("poll_every", c_int32), ("timing", c_int32),
-                ("ckpt_every", c_int32), ("graph", c_int32)]
+                ("ckpt_every", c_int32), ("graph", c_int32), ("tile_threshold", c_int32)]
 
 
 class DmptStats(ctypes.Structure):
@@ -469,13 +469,15 @@ def dmpt_selftest_mfma(stream=None) -> int:
 
 
 def dmpt_batch_init(Ns, noccs, ks, precision: str = "split_bf16", max_layers: int = 100,
-                    graph: bool = True, stream=None) -> c_void_p:
-    """dmpt_batch_init: workspace and tile tuning for a batch of problems."""
+                    graph: bool = True, stream=None, tile_threshold: int = -1) -> c_void_p:
+    """dmpt_batch_init: workspace and tile tuning for a batch of problems
+    (tile_threshold >= 0 fixes the tile classes instead of timing them)."""
     count = len(Ns)
     o = default_options()
     o.precision = PRECISION[precision]
     o.max_layers = max_layers
     o.graph = int(graph)
+    o.tile_threshold = int(tile_threshold)
     b = c_void_p()
     _check(LIB.dmpt_batch_init(byref(b), count, (c_int64 * count)(*Ns), (c_int64 * count)(*noccs),
                                (c_int32 * count)(*ks), byref(o), _stream(stream)))

@@ -315,6 +315,7 @@ void dmpt_default_options(dmpt_options* opt) {
   opt->timing = 0;
   opt->ckpt_every = 0;
   opt->graph = 1;
+  opt->tile_threshold = -1;
 }
 
 const char* dmpt_status_str(dmpt_status s) {

@@ -795,7 +795,12 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
     return bail(DMPT_EHIP, "stream/event creation failed");
-  if (autotune(b) != hipSuccess) return bail(DMPT_EHIP, "tile autotuning failed");
+  if (opt.tile_threshold >= 0) {
+    if (build_class_items(b, opt.tile_threshold) != hipSuccess)
+      return bail(DMPT_EHIP, "tile item set-up failed");
+  } else if (autotune(b) != hipSuccess) {
+    return bail(DMPT_EHIP, "tile autotuning failed");
+  }
   *out = b;
   return DMPT_OK;
 }

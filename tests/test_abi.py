@@ -32,11 +32,13 @@ def test_status_strings_and_defaults_without_gpu():
     assert _native.LIB.dmpt_status_str(-4).decode() == "DMPT_ENOCONV"
     o = _native.default_options()
     assert o.precision == _native.PRECISION["split_fp16"] and o.max_layers == 100
+    # the last field, written by the library: the structure layouts agree
+    assert o.graph == 1 and o.tile_threshold == -1
 
 
 def test_struct_sizes_match_c_layout():
     from paper_2203_09621_amd import _native
-    assert ctypes.sizeof(_native.DmptOptions) == 28
+    assert ctypes.sizeof(_native.DmptOptions) == 32
     assert ctypes.sizeof(_native.DmptProblemStats) == 8 * 4 + 8 * 4
     # 4+4+32+4+4+256 = 304, then 4 + 8 + 1 + 8 + 1 + 1 doubles, then 2 int32
     assert ctypes.sizeof(_native.DmptStats) == 304 + 8 * 23 + 8

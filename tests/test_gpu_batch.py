@@ -21,9 +21,9 @@ def _cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def _run(dm, probs, precision="split_bf16", graph=True, reps=1, max_layers=100):
+def _run(dm, probs, precision="split_bf16", graph=True, reps=1, max_layers=100, **kw):
     b = dm.dmpt_batch_init([p.N for p in probs], [p.nocc for p in probs], [p.k for p in probs],
-                           precision=precision, graph=graph, max_layers=max_layers)
+                           precision=precision, graph=graph, max_layers=max_layers, **kw)
     try:
         H0 = [_cuda(p.H0) for p in probs]
         H1 = [[_cuda(h) for h in p.H1] for p in probs]
@@ -149,6 +149,33 @@ def test_batch_ragged_sizes(dm):
     P0, P1, st, _ = res
     for i, p in enumerate(probs):
         print(f"ragged batch N={p.N} nocc={p.nocc} k={p.k}", flush=True)
+        r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+        e = max([exact.rel_fro(P0[i], r0)] + [exact.rel_fro(a, b) for a, b in zip(P1[i], r1s)])
+        assert st[i]["converged"] and e < TOL, (p.N, e)
+        q0, q1s, sst = dm.solve(_cuda(p.H0), [_cuda(h) for h in p.H1], p.nocc,
+                                precision="split_bf16")
+        assert st[i]["layers"] == sst["layers"]
+        assert np.array_equal(P0[i], q0.cpu().numpy())
+        for a, b in zip(P1[i], q1s):
+            assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_batch_both_tile_classes(dm):
+    """A fixed tile threshold of 256 puts the problems of padded size 256 on
+    the pair launch and the larger ones on the 256-row launch, in one batch:
+    every problem against the oracle and, bitwise, against its single solve."""
+    from oracle import exact
+    from workloads import dense_gapped_problem
+    sizes = [50, 200, 256, 300, 513, 777, 1024]
+    probs = [dense_gapped_problem(n, n // 2, 0.6, 700 + n, h1="diag", k=1 + i % 3)
+             for i, n in enumerate(sizes)]
+    (res,), info = _run(dm, probs, tile_threshold=256)
+    threshold, n256, n128 = info
+    assert threshold == 256 and n256 > 0 and n128 > 0, info
+    P0, P1, st, _ = res
+    for i, p in enumerate(probs):
+        print(f"two-class batch N={p.N} k={p.k} ({'pair' if p.N <= 256 else '256-row'} tiles)",
+              flush=True)
         r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
         e = max([exact.rel_fro(P0[i], r0)] + [exact.rel_fro(a, b) for a, b in zip(P1[i], r1s)])
         assert st[i]["converged"] and e < TOL, (p.N, e)

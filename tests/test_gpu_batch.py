@@ -185,3 +185,28 @@ def test_batch_both_tile_classes(dm):
         assert np.array_equal(P0[i], q0.cpu().numpy())
         for a, b in zip(P1[i], q1s):
             assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_batch_split_fp16(dm):
+    """The split-FP16 batch (the pair launch's FP16 form, hi scaled by 2^11,
+    and the 256-row class): every problem against the oracle and bitwise
+    against its single split-FP16 solve."""
+    from oracle import exact
+    from workloads import dense_gapped_problem
+    sizes = [3, 40, 129, 256, 300, 640]
+    probs = [dense_gapped_problem(n, max(1, n // 2), 0.6, 800 + n, h1="diag", k=1 + i % 3)
+             for i, n in enumerate(sizes)]
+    (res,), info = _run(dm, probs, precision="split_fp16", tile_threshold=256)
+    assert info[1] > 0 and info[2] > 0, info
+    P0, P1, st, _ = res
+    for i, p in enumerate(probs):
+        r0, r1s = exact.solve(p.H0, p.H1, p.nocc)
+        e = max([exact.rel_fro(P0[i], r0)] + [exact.rel_fro(a, b) for a, b in zip(P1[i], r1s)])
+        print(f"fp16 batch N={p.N} k={p.k}: worst error {e:.2e}", flush=True)
+        assert st[i]["converged"] and e < TOL, (p.N, e)
+        q0, q1s, sst = dm.solve(_cuda(p.H0), [_cuda(h) for h in p.H1], p.nocc,
+                                precision="split_fp16")
+        assert st[i]["layers"] == sst["layers"]
+        assert np.array_equal(P0[i], q0.cpu().numpy())
+        for a, b in zip(P1[i], q1s):
+            assert np.array_equal(a, b.cpu().numpy())

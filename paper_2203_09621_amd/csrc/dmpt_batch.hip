@@ -43,6 +43,12 @@ struct Chunk {
   int64_t q0, q1;                    // range of 4-element vectors of the padded storage
 };
 
+// One kOutB x kOutB block (bi, bj) of an output matrix (-1: P0, j: P1_j).
+struct OutBlock {
+  int32_t p, j, bi, bj;
+};
+constexpr int kOutB = 64;
+
 
 struct ProblemSummary {
   int32_t layers, d0_layer, converged, error;
@@ -216,25 +222,42 @@ __global__ void __launch_bounds__(kBlk) k_b_postdecide(const BatchProblem* P, co
 }
 
 // ------------------------------------------------------------------ outputs
-__global__ void __launch_bounds__(kBlk) k_b_out(const BatchProblem* P, const Chunk* C,
+// The pair launch keeps only the upper triangle of the FP32 masters current
+// (its mirror pass writes the 16-bit splits alone; the recursion reads the
+// masters only on upper tiles), so output block (bi, bj) is read from the
+// upper block (min, max) in coalesced rows and written through LDS,
+// transposed below the diagonal.  The 256-row launch's full masters are
+// symmetric, so the same read serves them.
+__global__ void __launch_bounds__(kBlk) k_b_out(const BatchProblem* P, const OutBlock* B,
                                                double* const* p0tab, double* const* p1tab) {
-  const Chunk c = C[blockIdx.x];
-  const BatchProblem& b = P[c.p];
+  __shared__ float tile[kOutB][kOutB + 1];
+  const OutBlock ob = B[blockIdx.x];
+  const BatchProblem& b = P[ob.p];
   const LayerState* st = b.st;
   const float* src;
   double* dst;
-  if (c.j < 0) {
+  if (ob.j < 0) {
     src = b.s_master;
     dst = p0tab[b.h0_index];
   } else {
-    const int L = st->d1[c.j] && st->d1_layer[c.j] > 0 ? st->d1_layer[c.j] - 1 : st->n;
-    src = b.s1buf[c.j][L & 1];
-    dst = p1tab[b.h1_first + c.j];
+    const int L = st->d1[ob.j] && st->d1_layer[ob.j] > 0 ? st->d1_layer[ob.j] - 1 : st->n;
+    src = b.s1buf[ob.j][L & 1];
+    dst = p1tab[b.h1_first + ob.j];
   }
   if (!dst) return;
-  for (int64_t q = c.q0 * 4 + threadIdx.x; q < c.q1 * 4; q += kBlk) {
-    const int64_t r = q / b.ld, col = q - r * b.ld;
-    if (r < b.n && col < b.n) dst[r * b.n + col] = (double)src[q];
+  const int64_t si = (int64_t)min(ob.bi, ob.bj) * kOutB, sj = (int64_t)max(ob.bi, ob.bj) * kOutB;
+  for (int e = threadIdx.x; e < kOutB * kOutB; e += kBlk) {
+    const int r = e / kOutB, c = e % kOutB;
+    const int64_t gr = si + r, gc = sj + c;
+    tile[r][c] = (gr < b.n && gc < b.n) ? src[gr * b.ld + gc] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kOutB * kOutB; e += kBlk) {
+    const int r = e / kOutB, c = e % kOutB;
+    const int64_t gr = (int64_t)ob.bi * kOutB + r, gc = (int64_t)ob.bj * kOutB + c;
+    if (gr >= b.n || gc >= b.n) continue;
+    const bool up = ob.bi < ob.bj || (ob.bi == ob.bj && r <= c);
+    dst[gr * b.n + gc] = (double)(up ? tile[r][c] : tile[c][r]);
   }
 }
 
@@ -348,6 +371,8 @@ struct dmpt_batch {
   Chunk* dc1 = nullptr;
   std::vector<TraceBlock> tb;                  // diagonal blocks of Tr X
   TraceBlock* dtb = nullptr;
+  std::vector<OutBlock> ob;                    // output blocks of every P0 and P1_j
+  OutBlock* dob = nullptr;
   double* part_tr = nullptr;                   // per diagonal block: trace partial
   double* part_g = nullptr;                    // per diagonal block: Gershgorin partials (3)
   double* part1m = nullptr;                    // per S1 chunk: max |H1|
@@ -593,9 +618,7 @@ hipError_t enqueue_response(dmpt_batch* b, hipStream_t s) {
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_b_out, dim3(b->c0.size()), dim3(kBlk), 0, s, b->dp, b->dc0, b->p0tab,
-                     b->p1tab);
-  hipLaunchKernelGGL(k_b_out, dim3(b->c1.size()), dim3(kBlk), 0, s, b->dp, b->dc1, b->p0tab,
+  hipLaunchKernelGGL(k_b_out, dim3(b->ob.size()), dim3(kBlk), 0, s, b->dp, b->dob, b->p0tab,
                      b->p1tab);
   hipLaunchKernelGGL(k_b_summary, dim3(P), dim3(kWave), 0, s, b->dp, b->dsum);
   return hipGetLastError();
@@ -713,6 +736,10 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
     q.tr_first = (int)b->tb.size();
     q.tr_count = (int)((q.n + 31) / 32);
     for (int r = 0; r < q.tr_count; ++r) b->tb.push_back(TraceBlock{p, r});
+    const int nob = (int)((q.n + kOutB - 1) / kOutB);
+    for (int j = -1; j < q.k; ++j)
+      for (int bi = 0; bi < nob; ++bi)
+        for (int bj = 0; bj < nob; ++bj) b->ob.push_back(OutBlock{p, j, bi, bj});
     for (int c = 0; c < nch; ++c)
       b->c0.push_back(Chunk{p, -1, (int64_t)c * kChunkVec, std::min<int64_t>(vec, (int64_t)(c + 1) * kChunkVec)});
     for (int j = 0; j < q.k; ++j) {
@@ -737,6 +764,7 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
   get((void**)&b->dc0, sizeof(Chunk) * b->c0.size());
   get((void**)&b->dc1, sizeof(Chunk) * b->c1.size());
   get((void**)&b->dtb, sizeof(TraceBlock) * b->tb.size());
+  get((void**)&b->dob, sizeof(OutBlock) * b->ob.size());
   get((void**)&b->part_tr, sizeof(double) * b->tb.size());
   get((void**)&b->part_g, sizeof(double) * 3 * b->tb.size());
   get((void**)&b->part1m, sizeof(double) * b->c1.size());
@@ -790,6 +818,8 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
       hipMemcpy(b->dc1, b->c1.data(), sizeof(Chunk) * b->c1.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(b->dtb, b->tb.data(), sizeof(TraceBlock) * b->tb.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->dob, b->ob.data(), sizeof(OutBlock) * b->ob.size(), hipMemcpyHostToDevice) !=
           hipSuccess)
     return bail(DMPT_EHIP, "workspace set-up failed");
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||

@@ -938,7 +938,10 @@ k_products_pair(const ProductArgs a) {
       }
     }
     lds_barrier();
-    // mirror block: row lc of the mirror gets T rows 4 qd .. 4 qd + 3 of column lc
+    // mirror block: row lc of the mirror gets T rows 4 qd .. 4 qd + 3 of column
+    // lc, in the 16-bit splits only (the next products read whole row panels);
+    // the FP32 masters are read only on upper tiles, and the outputs are
+    // mirrored when they are copied out
     if (upd) {
       for (int e = tid; e < BN * (SR / 4); e += NT) {
         const int qd = e % (SR / 4), lc = e / (SR / 4);
@@ -958,14 +961,12 @@ k_products_pair(const ProductArgs a) {
         const int64_t grow = (h ? c0_1 : c0_0) + lcl, gcol = (h ? r0_1 : r0_0) + lr;
         const int64_t pi = panel_index(grow, gcol, pdim);
         if (!diag || lr + 3 < lcl) {
-          *(f32x4*)(Mw + grow * ld + gcol) = v;
           *(U4*)(Hw + pi) = U4{hh[0], hh[1], hh[2], hh[3]};
           *(U4*)(Lw + pi) = U4{ll[0], ll[1], ll[2], ll[3]};
         } else {
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (lr + q < lcl) {
-              Mw[grow * ld + gcol + q] = v[q];
               Hw[pi + q] = hh[q];
               Lw[pi + q] = ll[q];
             }

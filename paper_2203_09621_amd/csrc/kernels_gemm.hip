@@ -920,7 +920,10 @@ k_products_pair(const ProductArgs a) {
           split_one<T16>(sn[q], esplit, S::kShift, hh + q, ll + q);
         }
         if (!upd) continue;
-        *(f32x4*)(T + tr * PT + lc) = sn;      // for the mirror pass
+        // for the mirror pass: the splits, packed hi << 16 | lo, in place of X
+        typedef uint32_t P4 __attribute__((ext_vector_type(4)));
+        *(P4*)(T + tr * PT + lc) = P4{((uint32_t)hh[0] << 16) | ll[0], ((uint32_t)hh[1] << 16) | ll[1],
+                                      ((uint32_t)hh[2] << 16) | ll[2], ((uint32_t)hh[3] << 16) | ll[3]};
         const int64_t pi = panel_index(grow, gcol, pdim);   // four columns, one panel row
         if (!diag || lr < lcl) {
           *(f32x4*)(Mw + grow * ld + gcol) = sn;
@@ -939,7 +942,8 @@ k_products_pair(const ProductArgs a) {
     }
     lds_barrier();
     // mirror block: row lc of the mirror gets T rows 4 qd .. 4 qd + 3 of column
-    // lc, in the 16-bit splits only (the next products read whole row panels);
+    // lc, in the 16-bit splits only (the next products read whole row panels,
+    // and the direct block left the splits in T);
     // the FP32 masters are read only on upper tiles, and the outputs are
     // mirrored when they are copied out
     if (upd) {
@@ -951,12 +955,12 @@ k_products_pair(const ProductArgs a) {
         const int tr = 4 * qd;
         const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
         if (diag && lr >= lcl) continue;       // lr + q < lcl for some q needs lr < lcl
-        f32x4 v;
         uint16_t hh[4], ll[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          v[q] = T[(tr + q) * PT + lc];
-          split_one<T16>(v[q], esplit, S::kShift, hh + q, ll + q);
+          const uint32_t u = __builtin_bit_cast(uint32_t, T[(tr + q) * PT + lc]);
+          hh[q] = (uint16_t)(u >> 16);
+          ll[q] = (uint16_t)(u & 0xffffu);
         }
         const int64_t grow = (h ? c0_1 : c0_0) + lcl, gcol = (h ? r0_1 : r0_0) + lr;
         const int64_t pi = panel_index(grow, gcol, pdim);

@@ -176,6 +176,7 @@ hipError_t launch_products_fused(dmpt_precision prec, int tile, const ProductArg
                                  hipStream_t s);
 // The same on items of two 128 x 128 tiles that share a row or a column band
 // (TileItem::ti2, tj2), one workgroup per CU: the batch's small-tile class.
+// First-order items only (X, X1_j): no problem may have a second-order slot.
 hipError_t launch_products_pair(dmpt_precision prec, const ProductArgs& a, hipStream_t s);
 // N_X = Tr X_n of the coming fused products, before them: the diagonal 32 x 32
 // fragments of X_n = S_{n-1}^2, one wave each, with the product kernel's MFMA

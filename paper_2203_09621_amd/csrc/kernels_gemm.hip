@@ -610,9 +610,10 @@ k_products_pair(const ProductArgs a) {
   const int csrc = lsl ^ ((lrow >> SWZ) & (CH - 1));
   const int voff = lrow * kPanelK + csrc * 8;
 
-  // Operands of one item: panels per product p, Q<p> = [hi_A, lo_A, hi_B, lo_B]
-  // (X: S S;  X1_j: S S1_j, S1_j S), panel-major (the k-tile kt of row tile I is
-  // the contiguous block I * kblocks + kt of kPanelRows x kPanelK elements).
+  // Operands of one item: the split of S and of T = S1_j (X: T = S); product 0
+  // is S T, product 1 (responses) T S.  Panel-major storage: the k-tile kt of
+  // row tile I is the contiguous block I * kblocks + kt of kPanelRows x
+  // kPanelK elements.
   struct Ops {
     TileItem it;
     int sexp, kt_per, ktiles, colp;            // colp: the tiles share their B panels
@@ -663,11 +664,9 @@ k_products_pair(const ProductArgs a) {
     }
     return false;
   };
-  // k-tile t0 of an item; past the end the last tile is fetched again into a
-  // stage nobody reads any more.  One load round moves one array.
-  // The fetch plan in scalar registers: an item's values come back from
-  // memory in vector registers, and carried from one item to the next they
-  // stay there unless read out here once per item.
+  // The fetch plan of the current item, read into scalar registers once per
+  // item: values carried across the item loop can end up in vector registers,
+  // and every load would then form its address per lane.
   struct Plan {
     const uint16_t* q[4];
     int64_t offx, offy0, offy1;
@@ -685,6 +684,8 @@ k_products_pair(const ProductArgs a) {
     pl.colp = uni(o.colp);
     return pl;
   };
+  // k-tile t0 of an item; past the end the last tile is fetched again into a
+  // stage nobody reads any more.  One load round moves one array.
   struct Fetch { const uint16_t* q[NARR]; u32x4* dst; };
   auto prep = [&](const Plan& o, int t0) {
     Fetch f;

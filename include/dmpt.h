@@ -233,7 +233,8 @@ dmpt_status dmpt_batch_response(dmpt_batch* batch, const double* const* H0,
                                 dmpt_problem_stats* st, double* ms);
 
 /* Tile classes the autotuner chose: problems with padded size <= *threshold
- * use 128-row tiles; number of tile items of each class. */
+ * use 128-row tiles; number of item positions of each launch (a 128-row item
+ * holds two tiles that share a row or a column band, or one). */
 dmpt_status dmpt_batch_info(const dmpt_batch* batch, int32_t* threshold, int32_t* n_items_256,
                             int32_t* n_items_128);
 

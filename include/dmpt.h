@@ -232,9 +232,10 @@ dmpt_status dmpt_batch_response(dmpt_batch* batch, const double* const* H0,
                                 const double* const* H1, double* const* P0, double* const* P1,
                                 dmpt_problem_stats* st, double* ms);
 
-/* Tile classes the autotuner chose: problems with padded size <= *threshold
- * use 128-row tiles; number of item positions of each launch (a 128-row item
- * holds two tiles that share a row or a column band, or one). */
+/* Tile classes the autotuner chose (or options.tile_threshold fixed):
+ * problems with padded size <= *threshold use 128-row tiles; number of item
+ * positions of each launch (a 128-row item holds two tiles that share a row
+ * or a column band, or one). */
 dmpt_status dmpt_batch_info(const dmpt_batch* batch, int32_t* threshold, int32_t* n_items_256,
                             int32_t* n_items_128);
 

@@ -764,6 +764,9 @@ dmpt_status dmpt_batch_init(dmpt_batch** out, int32_t count, const int64_t* N, c
   get((void**)&b->dc0, sizeof(Chunk) * b->c0.size());
   get((void**)&b->dc1, sizeof(Chunk) * b->c1.size());
   get((void**)&b->dtb, sizeof(TraceBlock) * b->tb.size());
+  if (b->ob.size() > (size_t)INT32_MAX || b->c0.size() > (size_t)INT32_MAX ||
+      b->c1.size() > (size_t)INT32_MAX || b->tb.size() > (size_t)INT32_MAX)
+    return bail(DMPT_EINVAL, "batch too large for one launch grid");
   get((void**)&b->dob, sizeof(OutBlock) * b->ob.size());
   get((void**)&b->part_tr, sizeof(double) * b->tb.size());
   get((void**)&b->part_g, sizeof(double) * 3 * b->tb.size());

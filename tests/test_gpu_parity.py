@@ -57,6 +57,49 @@ def test_config1_fp64_parity_and_sigma(dm, c1):
     assert abs(st["trace_p0"] - c1.nocc) < 1e-9 and abs(st["trace_p1"][0]) < 1e-9
 
 
+@pytest.mark.parametrize("n", [256, 300])
+def test_fp64_every_layer_matches_eigenbasis_recursion(dm, n):
+    """Layer by layer, the FP64 form's S_m and S1_m equal the recursion run
+    in the eigenbasis of H0 (the 2x2 block-function form of Sec. IV, one layer
+    at a time), which has no rounding in its traces or norms.  A context
+    capped at m layers stops with ENOCONV and returns S_m and S1_m.  Every
+    layer up to the earlier D1 layer is compared, the zeroth-order chain
+    frozen after D0 included; the dense FP64 recursion stays within about
+    2e-14 of the eigenbasis run over the same layers.  N = 300 leaves a ragged
+    44-row tail on the 128-row tiles."""
+    import torch
+    from oracle import eigsim, exact
+    from workloads import config1
+    p = config1(n=n)
+    _, _, v, se = eigsim.run(p.H0, p.H1, p.nocc, record=True)
+    _, _, full = _solve(dm, p, "fp64")
+    assert full["converged"]
+    assert full["d0_layer"] == se["d0_layer"]
+    d0 = se["d0_layer"]
+    last = min(full["d1_layer"][0], se["d1_layer"][0]) - 1
+    assert full["sigma"][:d0 - 1] == se["sigma"][:d0 - 1]
+    h0, h1 = _cuda(p.H0), _cuda(p.H1[0])
+    worst = [0.0, 0.0]
+    for m in range(1, last + 1):
+        S0 = torch.full_like(h0, float("nan"))
+        S1 = torch.full_like(h0, float("nan"))
+        ctx = dm.dmpt_init(h0, p.nocc, k_max=1, precision="fp64", max_layers=m)
+        try:
+            with pytest.raises(dm.DmptError) as ei:
+                dm.dmpt_response(ctx, [h1], P0=S0, P1s=[S1])
+        finally:
+            dm.dmpt_destroy(ctx)
+        assert ei.value.status == -4 and ei.value.stats["layers"] == m
+        x, (y,) = se["history"][m - 1]
+        s0e, s1e = eigsim.to_dense(x, y, v)
+        e0 = exact.rel_fro(S0.cpu().numpy(), s0e)
+        e1 = exact.rel_fro(S1.cpu().numpy(), s1e)
+        worst = [max(worst[0], e0), max(worst[1], e1)]
+        assert e0 < 1e-12 and e1 < 1e-12, (m, e0, e1)
+    print(f"N={n}: layers 1..{last} (D0 at {d0}) worst S0 {worst[0]:.2e} S1 {worst[1]:.2e}",
+          flush=True)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "split_fp16", "split_bf16"])
 def test_config1_reduced_precision(dm, c1, precision):
     P0, P1s, st = _solve(dm, c1, precision)

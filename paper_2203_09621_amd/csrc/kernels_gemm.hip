@@ -761,6 +761,9 @@ k_products_pair(const ProductArgs a) {
   const auto* pd = cst(a.probs + it.prob);
   const auto* fst = cst(pd->state);
   const int64_t ld = pd->ld, pdim = pd->pdim;
+  // rows and columns from kdim on stay zero (cleared at set-up; X = S^2 and
+  // the update keep them zero), so the epilogue neither reads nor stores them
+  const int64_t kd = pd->kdim;
   const int ti2 = uni(it.ti2), tj2 = uni(it.tj2);
   const bool single = ti2 < 0;
   const bool live = !(single && half);       // wave-uniform
@@ -892,9 +895,9 @@ k_products_pair(const ProductArgs a) {
         const int tr = e / BN, lc = e % BN;
         const int h = lc / BM, lcl = lc % BM;
         const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
-        const int64_t rb = h ? r0_1 : r0_0, cb = h ? c0_1 : c0_0;
-        sov[i] = (need_old && !(single && h))
-                     ? *(const f32x4*)(Mr + (rb + lr) * ld + cb + lcl)
+        const int64_t grow = (h ? r0_1 : r0_0) + lr, gcol = (h ? c0_1 : c0_0) + lcl;
+        sov[i] = (need_old && !(single && h) && grow < kd && gcol < kd)
+                     ? *(const f32x4*)(Mr + grow * ld + gcol)
                      : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
       }
 #pragma unroll
@@ -904,9 +907,12 @@ k_products_pair(const ProductArgs a) {
         const int h = lc / BM, lcl = lc % BM;
         if (single && h) continue;
         const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
+        const int64_t grow = (h ? r0_1 : r0_0) + lr, gcol = (h ? c0_1 : c0_0) + lcl;
+        // four columns from a multiple of 4: wholly inside kd or wholly past it
+        // (X is zero there, so the partials would gain exact zeros)
+        if (grow >= kd || gcol >= kd) continue;
         const bool diag = h ? diag1 : diag0;
         const f32x4 x = *(const f32x4*)(T + tr * PT + lc);
-        const int64_t grow = (h ? r0_1 : r0_0) + lr, gcol = (h ? c0_1 : c0_0) + lcl;
         const f32x4 so = sov[i];
         f32x4 sn;
         uint16_t hh[4], ll[4];
@@ -956,6 +962,8 @@ k_products_pair(const ProductArgs a) {
         const int tr = 4 * qd;
         const int lr = (tr >> 5) * WTM + m * 32 + (tr & 31);
         if (diag && lr >= lcl) continue;       // lr + q < lcl for some q needs lr < lcl
+        const int64_t grow = (h ? c0_1 : c0_0) + lcl, gcol = (h ? r0_1 : r0_0) + lr;
+        if (grow >= kd || gcol >= kd) continue;  // T holds splits only where the direct block ran
         uint16_t hh[4], ll[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -963,7 +971,6 @@ k_products_pair(const ProductArgs a) {
           hh[q] = (uint16_t)(u >> 16);
           ll[q] = (uint16_t)(u & 0xffffu);
         }
-        const int64_t grow = (h ? c0_1 : c0_0) + lcl, gcol = (h ? r0_1 : r0_0) + lr;
         const int64_t pi = panel_index(grow, gcol, pdim);
         if (!diag || lr + 3 < lcl) {
           *(U4*)(Hw + pi) = U4{hh[0], hh[1], hh[2], hh[3]};

@@ -495,3 +495,70 @@ def test_pair_launch_fetches_and_stores_in_bounds(N, k):
                 assert grow * ld + gcol + 4 <= Np * ld
                 pi = ((grow // 256) * kblocks + gcol // 32) * blk + (grow % 256) * 32 + gcol % 32
                 assert gcol % 32 + 4 <= 32 and pi + 4 <= Np * Np
+
+
+def _pair_epilogue_stores(r0, c0, kd):
+    """The pair epilogue's stores for one tile at (r0, c0) (the first tile of
+    an item, h = 0), as the kernel's index arithmetic forms them: a map
+    (row, col) -> number of split stores, the set of master stores, and
+    whether every staged entry the mirror pass reads was written as a split by
+    the direct pass of the same round."""
+    BN, SR, NT = 2 * P_BM, 32 * P_WGM, P_NT
+    ITER = SR * BN // (4 * NT)
+    diag = r0 == c0
+    split, master, reads_ok = {}, set(), True
+    for m in range(P_BM // P_WT):
+        staged = set()
+        for g in range(ITER):
+            e = (np.arange(NT) + g * NT) * 4
+            tr, lc = e // BN, e % BN
+            for t_r, l_c in zip(tr, lc):
+                h, lcl = l_c // P_BM, l_c % P_BM
+                if h:
+                    continue
+                lr = (t_r >> 5) * P_WT + m * 32 + (t_r & 31)
+                grow, gcol = r0 + lr, c0 + lcl
+                if grow >= kd or gcol >= kd:
+                    continue
+                staged.update((t_r, l_c + q) for q in range(4))
+                for q in range(4):
+                    if not diag or lr <= lcl + q:
+                        split[(grow, gcol + q)] = split.get((grow, gcol + q), 0) + 1
+                        master.add((grow, gcol + q))
+        for e in range(BN * (SR // 4)):
+            qd, lc = e % (SR // 4), e // (SR // 4)
+            h, lcl = lc // P_BM, lc % P_BM
+            if h:
+                continue
+            tr = 4 * qd
+            lr = (tr >> 5) * P_WT + m * 32 + (tr & 31)
+            if diag and lr >= lcl:
+                continue
+            grow, gcol = c0 + lcl, r0 + lr
+            if grow >= kd or gcol >= kd:
+                continue
+            reads_ok &= all((tr + q, lc) in staged for q in range(4))
+            for q in range(4):
+                if not diag or lr + q < lcl:
+                    split[(grow, gcol + q)] = split.get((grow, gcol + q), 0) + 1
+    return split, master, reads_ok
+
+
+@pytest.mark.parametrize("N,ti,tj", [(37, 0, 0), (300, 2, 2), (300, 0, 2), (300, 1, 2),
+                                     (256, 0, 1), (200, 1, 1)])
+def test_pair_epilogue_skips_only_the_zero_padding(N, ti, tj):
+    """The pair epilogue leaves out rows and columns from kd = N rounded up to
+    32 on (zero in every buffer).  Inside [0, kd)^2 the tile and its mirror
+    still get every split exactly once and the masters every element of the
+    upper side; the mirror pass reads only staged splits of the same round."""
+    kd = -(-N // 32) * 32
+    r0, c0 = ti * P_BM, tj * P_BM
+    split, master, reads_ok = _pair_epilogue_stores(r0, c0, kd)
+    assert reads_ok
+    rows = range(r0, min(r0 + P_BM, kd))
+    cols = range(c0, min(c0 + P_BM, kd))
+    want = {(i, j) for i in rows for j in cols if r0 != c0 or i <= j}
+    assert master == want
+    want_split = want | {(j, i) for (i, j) in want}
+    assert set(split) == want_split and set(split.values()) <= {1}
+    assert all(i < kd and j < kd for (i, j) in split)

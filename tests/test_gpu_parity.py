@@ -100,6 +100,47 @@ def test_fp64_every_layer_matches_eigenbasis_recursion(dm, n):
           flush=True)
 
 
+@pytest.mark.parametrize("precision", ["split_fp16", "split_bf16", "fp32"])
+def test_reduced_precision_every_layer_within_the_bar(dm, precision):
+    """The split and FP32 forms layer by layer against the eigenbasis
+    recursion at N = 300: every S_m and S1_m before D0, while both runs take
+    the same sigma, within the end-to-end bar of 1e-3.  Each form picks sigma
+    (Alg. 1) and fires Alg. 2's noise-floor test on its own traces; near
+    convergence the two sigma candidates differ by less than the form's
+    rounding, so a reduced form may take the other branch a few layers
+    before D0 (split BF16 here at layer 31 of 37), and D0 may move by one."""
+    import torch
+    from oracle import eigsim, exact
+    from workloads import config1
+    p = config1(n=300)
+    _, _, v, se = eigsim.run(p.H0, p.H1, p.nocc, record=True)
+    _, _, full = _solve(dm, p, precision)
+    assert full["converged"]
+    last = min(full["d0_layer"], se["d0_layer"]) - 1
+    last = next((i for i in range(last) if full["sigma"][i] != se["sigma"][i]), last)
+    assert last >= 25
+    h0, h1 = _cuda(p.H0), _cuda(p.H1[0])
+    worst = [0.0, 0.0]
+    for m in range(1, last + 1):
+        S0 = torch.full_like(h0, float("nan"))
+        S1 = torch.full_like(h0, float("nan"))
+        ctx = dm.dmpt_init(h0, p.nocc, k_max=1, precision=precision, max_layers=m)
+        try:
+            with pytest.raises(dm.DmptError) as ei:
+                dm.dmpt_response(ctx, [h1], P0=S0, P1s=[S1])
+        finally:
+            dm.dmpt_destroy(ctx)
+        assert ei.value.status == -4 and ei.value.stats["layers"] == m
+        x, (y,) = se["history"][m - 1]
+        s0e, s1e = eigsim.to_dense(x, y, v)
+        e0 = exact.rel_fro(S0.cpu().numpy(), s0e)
+        e1 = exact.rel_fro(S1.cpu().numpy(), s1e)
+        worst = [max(worst[0], e0), max(worst[1], e1)]
+        assert e0 < SPLIT_TOL and e1 < SPLIT_TOL, (m, e0, e1)
+    print(f"{precision} N=300: layers 1..{last} worst S0 {worst[0]:.2e} S1 {worst[1]:.2e}",
+          flush=True)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "split_fp16", "split_bf16"])
 def test_config1_reduced_precision(dm, c1, precision):
     P0, P1s, st = _solve(dm, c1, precision)

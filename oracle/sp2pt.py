@@ -65,8 +65,8 @@ def run(h0: np.ndarray, h1s, nocc: int, max_layers: int = 100, record: bool = Fa
         if x2 is not None and ctl.second_order(lambda: np.linalg.norm(s2 - x2)):
             s2 = sig * x2 + (1 - sig) * s2
         del s0_prev
-        if record:
-            hist.append((s0.copy(), [s.copy() for s in s1]))
+        if record:   # (S_n, [S1_n]) and, with order2, S2_n
+            hist.append((s0.copy(), [s.copy() for s in s1]) + ((s2.copy(),) if order2 else ()))
     st = ctl.stats()
     st["eps1"], st["epsN"] = bounds
     if order2:

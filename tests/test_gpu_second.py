@@ -66,6 +66,41 @@ def test_fp64_second_order_parity_and_layers(dm, with_h2):
     assert abs(st["trace_p1"][1]) < 1e-9
 
 
+def test_fp64_second_order_every_layer(dm):
+    """Layer by layer, the FP64 form's S_m, S1_m and S2_m (three-product X2
+    items) equal the dense FP64 recursion of Sec. III with k = 2 within 1e-12:
+    a context capped at m layers stops with ENOCONV and returns them.  Layers
+    up to the first D test that the two runs do not pass together."""
+    import torch
+    from oracle import exact, sp2pt
+    p, h2 = _problem(256, 1001, with_h2=True)
+    _, _, ref = sp2pt.run(p.H0, p.H1, p.nocc, order2=True, h2=h2, record=True)
+    _, _, _, full = _run(dm, p, h2, "fp64")
+    assert full["converged"]
+    last = min(full["d0_layer"], ref["d0_layer"]) - 1
+    if full["d0_layer"] == ref["d0_layer"]:
+        last = min(full["d1_layer"][0], ref["d1_layer"][0]) - 1
+    assert last >= 20
+    assert full["sigma"][:last] == ref["sigma"][:last]
+    h0, h1, hh2 = _cuda(p.H0), _cuda(p.H1[0]), _cuda(h2)
+    worst = [0.0, 0.0, 0.0]
+    for m in range(1, last + 1):
+        outs = [torch.full_like(h0, float("nan")) for _ in range(3)]
+        ctx = dm.dmpt_init(h0, p.nocc, k_max=2, precision="fp64", max_layers=m)
+        try:
+            with pytest.raises(dm.DmptError) as ei:
+                dm.dmpt_response2(ctx, h1, hh2, P0=outs[0], P1=outs[1], P2=outs[2])
+        finally:
+            dm.dmpt_destroy(ctx)
+        assert ei.value.status == -4 and ei.value.stats["layers"] == m
+        s0, (s1,), s2 = ref["history"][m - 1]
+        errs = [exact.rel_fro(o.cpu().numpy(), r) for o, r in zip(outs, (s0, s1, s2))]
+        worst = [max(w, e) for w, e in zip(worst, errs)]
+        assert max(errs) < 1e-12, (m, errs)
+    print(f"second order fp64: layers 1..{last} worst S {worst[0]:.2e} S1 {worst[1]:.2e} "
+          f"S2 {worst[2]:.2e}", flush=True)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "split_fp16", "split_bf16"])
 def test_reduced_precision_second_order(dm, precision):
     p, h2 = _problem(256, 1001)

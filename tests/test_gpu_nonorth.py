@@ -38,6 +38,30 @@ def test_inverse_factor_fp64(dm, prob):
     assert np.array_equal(Zh, Zh.T)
 
 
+def test_inverse_factor_every_iterate_fp64(dm, prob):
+    """Each iterate Z_m of the Sec. II.A recursion (a call capped at m updates
+    stops with ENOCONV and returns Z_m and the residual of Z_m) equals the
+    oracle's iterate within 1e-12, relative to its largest entry."""
+    import torch
+    from oracle import exact
+    _, it_total, _ = exact.inverse_factor(prob.O, tol=1e-12)
+    assert it_total >= 5
+    O = _cuda(prob.O)
+    worst = 0.0
+    for m in range(1, it_total):
+        Zt = torch.full_like(O, float("nan"))
+        with pytest.raises(dm.DmptError) as ei:
+            dm.dmpt_inverse_factor(O, precision="fp64", max_iter=m, tol=1e-300, Z=Zt)
+        assert ei.value.status == -4 and ei.value.stats["iters"] == m
+        z_ref, it_ref, r_ref = exact.inverse_factor(prob.O, tol=0.0, max_iter=m)
+        assert it_ref == m
+        d = float(np.abs(Zt.cpu().numpy() - z_ref).max() / np.abs(z_ref).max())
+        worst = max(worst, d)
+        assert d < 1e-12, (m, d)
+        assert abs(ei.value.stats["err"] - r_ref) <= 1e-9 * max(r_ref, 1e-3), (m, r_ref)
+    print(f"inverse factor fp64: iterates 1..{it_total - 1} within {worst:.2e}", flush=True)
+
+
 def test_inverse_factor_fp32(dm, prob):
     Z, it, err = dm.dmpt_inverse_factor(_cuda(prob.O), precision="fp32", tol=1e-4)
     Zh = Z.cpu().numpy()

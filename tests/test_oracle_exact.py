@@ -182,7 +182,8 @@ def test_step_divided_differences():
     g = exact.step_divided_differences(e, p.nocc)
     mu = 0.5 * (e[p.nocc - 1] + e[p.nocc])
     beta = 80.0 / (e[p.nocc] - e[p.nocc - 1])
-    f = 1.0 / (1.0 + np.exp(beta * (e - mu)))
+    from scipy.special import expit
+    f = expit(-beta * (e - mu))          # the Fermi function, without overflow
     assert np.abs(f - (e < mu)).max() < 1e-16
     de = e[:, None] - e[None, :]
     off = ~np.eye(len(e), dtype=bool)

@@ -93,10 +93,12 @@ def measured_traffic(workload, precision):
     path = os.path.join(ROOT, "profiles", "k_products_split_N16384_hbm_counters.md")
     src = os.path.join(ROOT, "paper_2203_09621_amd", "csrc", "kernels_gemm.hip")
     try:
-        m = re.search(r"```json\n(.*?)```", open(path).read(), re.S)
+        with open(path) as fh:
+            m = re.search(r"```json\n(.*?)```", fh.read(), re.S)
         data = json.loads(m.group(1))
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    except Exception:
+        with open(src, "rb") as fh:
+            cur = hashlib.sha256(fh.read()).hexdigest()[:16]
+    except (OSError, AttributeError, ValueError):
         return None
     if data.get("source_sha256_16") != cur:
         return None

@@ -130,11 +130,7 @@ def cpu_baseline(p, workload, layers, full=True):
     62 s measured)."""
     from oracle import exact
     from workloads import banded_gapped_problem, dense_gapped_problem
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count()
+    cores = _host_cores()
     ns = p.N if full else min(p.N, 8192)
     if ns == p.N:
         q = p
@@ -252,12 +248,7 @@ def adjoint_main(args, torch, dm):
         if not args.no_oracle:
             out["rel_fro_err"] = {"dL_dH0": e0, "dL_dH1": e1}
         if not args.no_cpu:
-            cores = os.cpu_count()
-            try:
-                from threadpoolctl import threadpool_info
-                cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
-            except Exception:  # pragma: no cover
-                pass
+            cores = _host_cores()
             out["cpu_baseline"] = {"value": round(1.0 / t_or, 4), "unit": out["unit"],
                                    "cores": cores, "kind": "oracle",
                                    "sample": f"closed-form FP64 gradients (eigh + divided "
@@ -331,12 +322,7 @@ def batch_main(args, torch, dm):
         # one pass of the FP64 oracle over the whole batch gives both the
         # errors and the host-core baseline (about 30 s of CPU work)
         from oracle import exact
-        cores = os.cpu_count()
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
-        except Exception:  # pragma: no cover
-            pass
+        cores = _host_cores()
         P0h = [x.cpu().numpy() for x in P0]
         P1h = [[x.cpu().numpy() for x in xs] for xs in P1]
         errs = []
@@ -362,10 +348,11 @@ def batch_main(args, torch, dm):
 
 
 def _host_cores():
+    """Threads the BLAS/LAPACK pools under the CPU oracle use."""
     try:
         from threadpoolctl import threadpool_info
         return max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
+    except ImportError:  # pragma: no cover
         return os.cpu_count()
 
 

@@ -1418,12 +1418,16 @@ __global__ void __launch_bounds__(kWave) k_trace_diag(const ProblemDesc* probs,
   // wait on them would be a full drain)
   typedef const __attribute__((address_space(1))) V GV;
   V h[2][U][KS], l[2][U][KS];
-  auto fetch = [&](V (&hh)[U][KS], V (&ll)[U][KS], int64_t b0) {
+  // batch i holds blocks i U .. min(kb, (i + 1) U) - 1; its fetch clamps the
+  // block index to kb - 1, so every load is issued and stays in the buffer
+  // (the copies past the end are never multiplied)
+  auto fetch = [&](V (&hh)[U][KS], V (&ll)[U][KS], int64_t i) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) {
-        const int64_t off = base + (b0 + u) * (kPanelRows * kPanelK) + 16 * kk;
+        const int64_t b = min(i * U + u, kb - 1);
+        const int64_t off = base + b * (kPanelRows * kPanelK) + 16 * kk;
         hh[u][kk] = *(GV*)(hi + off);
         ll[u][kk] = *(GV*)(lo + off);
       }
@@ -1433,34 +1437,31 @@ __global__ void __launch_bounds__(kWave) k_trace_diag(const ProblemDesc* probs,
     acc = S::mma(ah, al, acc);
     acc = S::mma(al, ah, acc);
   };
-  auto consume = [&](const V (&hh)[U][KS], const V (&ll)[U][KS]) {
+  const int64_t nb = (kb + U - 1) / U;       // batches, the last one possibly partial
+  auto consume = [&](const V (&hh)[U][KS], const V (&ll)[U][KS], int64_t i) {
+    const int cnt = (int)min((int64_t)U, kb - i * U);   // uniform
 #pragma unroll
     for (int u = 0; u < U; ++u)
+      if (u < cnt) {
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) mma3(hh[u][kk], ll[u][kk]);
+        for (int kk = 0; kk < KS; ++kk) mma3(hh[u][kk], ll[u][kk]);
+      }
   };
-  // Pairs of batches; every fetch is unconditional (a branch around one
-  // would make the wait before the next MFMAs cover it too): the last one
-  // fetches the final batch again, and nothing reads it.
-  const int64_t np2 = kb / (2 * U);
-  if (np2 > 0) fetch(h[0], l[0], 0);
+  // Pairs of batches, the next batch's loads in flight while this one's
+  // MFMAs run; every fetch is unconditional (a branch around one would make
+  // the wait before the next MFMAs cover it too): past the last batch the
+  // last one is fetched again, and nothing reads it.
+  fetch(h[0], l[0], 0);
   // (scheduling fences keep each batch's loads ahead of the other's MFMAs)
-  for (int64_t q = 0; q < np2; ++q) {
-    fetch(h[1], l[1], (2 * q + 1) * U);
+  for (int64_t q = 0; q < nb; q += 2) {
+    fetch(h[1], l[1], q + 1 < nb ? q + 1 : q);
     __builtin_amdgcn_sched_barrier(0);
-    consume(h[0], l[0]);
+    consume(h[0], l[0], q);
     __builtin_amdgcn_sched_barrier(0);
-    fetch(h[0], l[0], (q + 1 < np2 ? 2 * q + 2 : 2 * q + 1) * U);
+    fetch(h[0], l[0], q + 2 < nb ? q + 2 : q);
     __builtin_amdgcn_sched_barrier(0);
-    consume(h[1], l[1]);
+    if (q + 1 < nb) consume(h[1], l[1], q + 1);
     __builtin_amdgcn_sched_barrier(0);
-  }
-  for (int64_t b = 2 * np2 * U; b < kb; ++b) {   // the remaining blocks
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const int64_t off = base + b * (kPanelRows * kPanelK) + 16 * kk;
-      mma3(*(const V*)(hi + off), *(const V*)(lo + off));
-    }
   }
   // lane (c, h) holds the diagonal element of column c when h = (c / 4) % 2
   const int c = lane & 31;

@@ -25,7 +25,9 @@
  *     is enqueued on it; the call returns after the results are written and
  *     the statistics are readable (one synchronisation at the end).
  *   - No exception crosses the ABI.  A non-OK status leaves the outputs
- *     undefined; dmpt_last_error() gives a human-readable reason.
+ *     undefined, except ENOCONV from a capped iteration: the outputs then
+ *     hold its last layer (or iterate), as each call states.
+ *     dmpt_last_error() gives a human-readable reason.
  *   - One context per stream; contexts are not thread-safe.
  *   - The library owns its workspace (allocated in dmpt_init, released by
  *     dmpt_destroy); H0 may be freed after dmpt_init returns.
@@ -135,8 +137,9 @@ dmpt_status dmpt_response(dmpt_ctx* ctx, const double* const* H1, int32_t k, dou
  * stopping tests for first order only; S2 takes Algorithm 3's test on
  * ||S2 - X2||_F from two layers after the D1 layer on, and P2 is S2 of the
  * layer before that test fired.  In `st`, index 1 of d1_layer, idem1 and
- * trace_p1 refers to P2.  P0 may be NULL.  Errors as dmpt_response; the
- * adjoint does not cover this form. */
+ * trace_p1 refers to P2.  P0 may be NULL.  Errors as dmpt_response (with
+ * ENOCONV, P0, P1 and P2 hold the last layer); the adjoint does not cover
+ * this form. */
 dmpt_status dmpt_response2(dmpt_ctx* ctx, const double* H1, const double* H2, double* P0,
                            double* P1, double* P2, dmpt_stats* st);
 
@@ -227,7 +230,9 @@ dmpt_status dmpt_batch_init(dmpt_batch** batch, int32_t count, const int64_t* N,
  * as a whole or per entry) and P1[i] receive the results (device FP64, N x N
  * of their problem).  st (count entries, may be NULL) receives per-problem
  * statistics, ms (may be NULL) the device time.  Returns ENOCONV if some
- * problem hit the layer cap, ENONFINITE on a non-finite value. */
+ * problem hit the layer cap (every output then holds its problem's last
+ * layer, and st tells which problems converged), ENONFINITE on a
+ * non-finite value. */
 dmpt_status dmpt_batch_response(dmpt_batch* batch, const double* const* H0,
                                 const double* const* H1, double* const* P0, double* const* P1,
                                 dmpt_problem_stats* st, double* ms);
@@ -277,7 +282,8 @@ dmpt_status dmpt_contract_noalloc(const double* const* A, int32_t na, const doub
  * iters and err (may be NULL) receive the updates done and the last residual.
  * Writes Z (device FP64 N x N).  Errors: EINVAL, ENOTSUP (other precisions),
  * ENOMEM, EHIP, ENONFINITE (O not positive definite: divergence), ENOCONV
- * (tol not reached). */
+ * (tol not reached in max_iter updates; Z then holds the last iterate and
+ * err its residual). */
 dmpt_status dmpt_inverse_factor(int32_t precision, const double* O, int64_t N, double* Z,
                                 int32_t max_iter, double tol, int32_t* iters, double* err,
                                 void* stream);

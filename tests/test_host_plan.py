@@ -562,3 +562,41 @@ def test_pair_epilogue_skips_only_the_zero_padding(N, ti, tj):
     want_split = want | {(j, i) for (i, j) in want}
     assert set(split) == want_split and set(split.values()) <= {1}
     assert all(i < kd and j < kd for (i, j) in split)
+
+
+def _trace_walk(kb, U=8):
+    """The trace kernel's batch loop over kb panel blocks: (fetched block
+    indices, blocks multiplied in order)."""
+    nb = -(-kb // U)
+    fetched, used = [], []
+    bufs = [None, None]
+
+    def fetch(slot, i):
+        blocks = [min(i * U + u, kb - 1) for u in range(U)]
+        fetched.extend(blocks)
+        bufs[slot] = (i, blocks)
+
+    def consume(slot, i):
+        j, blocks = bufs[slot]
+        assert j == i                                   # the buffer holds batch i
+        cnt = min(U, kb - i * U)
+        used.extend(blocks[:cnt])
+
+    fetch(0, 0)
+    for q in range(0, nb, 2):
+        fetch(1, q + 1 if q + 1 < nb else q)
+        consume(0, q)
+        fetch(0, q + 2 if q + 2 < nb else q)
+        if q + 1 < nb:
+            consume(1, q + 1)
+    return fetched, used
+
+
+@pytest.mark.parametrize("kb", list(range(1, 40)) + [512, 513])
+def test_trace_batches_cover_every_block_once_in_order(kb):
+    """Every fetch stays inside [0, kb) and the MFMAs take blocks 0 .. kb - 1
+    exactly once, in k order (the product's sequence, so the diagonal stays
+    bitwise the product's)."""
+    fetched, used = _trace_walk(kb)
+    assert min(fetched) >= 0 and max(fetched) <= kb - 1
+    assert used == list(range(kb))

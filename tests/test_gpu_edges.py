@@ -1,7 +1,7 @@
 """Edge cases and full-size parity of the HIP path against the FP64 oracle:
 the smallest problem (N = 2, the 2x2 closed form), extreme occupations, a zero
-perturbation, the maximum number of responses, and configurations 2 and 3 at
-their full sizes (N = 4096 with three coordinate perturbations; N = 16384
+perturbation, the maximum number of responses, empty inputs (refused), and
+configurations 2 and 3 at their full sizes (N = 4096 with three coordinate perturbations; N = 16384
 banded against the exact factored oracle)."""
 import numpy as np
 import pytest
@@ -109,3 +109,36 @@ def test_full_size_configuration3(dm):
     print(f"configuration 3: layers {st['layers']} errors P0 {e0:.2e} P1 {e1:.2e}", flush=True)
     assert st["converged"] and e0 < SPLIT_TOL and e1 < SPLIT_TOL
     assert abs(st["trace_p0"] - p.nocc) < 1e-2
+
+
+def test_empty_inputs_are_refused(dm):
+    """Empty inputs return EINVAL before any device work: a 0 x 0 Hamiltonian,
+    overlap, contraction operand or layer-product input, a batch of no
+    problems, a batch holding an empty problem, and a contraction over no
+    matrices."""
+    import torch
+    from ctypes import c_double, c_void_p
+    from paper_2203_09621_amd import _native
+    e = torch.empty((0, 0), dtype=torch.float64, device="cuda")
+    a = _cuda(np.eye(4))
+    calls = [
+        lambda: dm.dmpt_init(e, 0),
+        lambda: dm.dmpt_inverse_factor(e),
+        lambda: dm.dmpt_contract([e], [e]),
+        lambda: dm.dmpt_contract_noalloc([e], [e]),
+        lambda: dm.dmpt_batch_init([], [], []),
+        lambda: dm.dmpt_batch_init([0, 64], [0, 32], [1, 1]),
+    ]
+    for call in calls:
+        with pytest.raises(dm.DmptError) as ei:
+            call()
+        assert ei.value.status == -1
+    out = (c_double * 1)()
+    one = (c_void_p * 1)(a.data_ptr())
+    none = (c_void_p * 1)()
+    for fn in (_native.LIB.dmpt_contract, _native.LIB.dmpt_contract_noalloc):
+        assert fn(none, 0, one, 1, 4, out, None) == -1
+        assert fn(one, 1, none, 0, 4, out, None) == -1
+        assert fn(one, 1, one, 1, 0, out, None) == -1
+    eps = (c_double * 2)()
+    assert _native.LIB.dmpt_gershgorin(c_void_p(a.data_ptr()), 0, eps, None) == -1

@@ -57,7 +57,10 @@ typedef enum {
 typedef enum {
   DMPT_FP64 = 0,        /* FP64 MFMA products, FP64 layer state (the plain FP64 GPU form) */
   DMPT_FP32 = 1,        /* FP32 MFMA products, FP32 layer state */
-  DMPT_SPLIT_BF16 = 2,  /* X ~ hi*hi + hi*lo + lo*hi with BF16 hi/lo parts, FP32 accumulate */
+  DMPT_SPLIT_BF16 = 2,  /* X ~ hi*hi + hi*lo + lo*hi with BF16 hi/lo parts, FP32 accumulate;
+                           16 significant bits (split FP16: 22), so the noise-floor D0 test
+                           fires earlier: P1 errors near 1e-3 on small problems with a narrow
+                           relative gap (up to 2e-3 seen at N = 16) */
   DMPT_SPLIT_FP16 = 3   /* same with FP16 hi/lo parts; lo and S1 carry power-of-two scales */
 } dmpt_precision;
 

@@ -1,7 +1,7 @@
 """Edge cases and full-size parity of the HIP path against the FP64 oracle:
 the smallest problem (N = 2, the 2x2 closed form), extreme occupations, a zero
-perturbation, the maximum number of responses, empty inputs (refused), and
-configurations 2 and 3 at their full sizes (N = 4096 with three coordinate perturbations; N = 16384
+perturbation, the maximum number of responses, empty inputs (refused), a
+narrow gap, and configurations 2 and 3 at their full sizes (N = 4096 with three coordinate perturbations; N = 16384
 banded against the exact factored oracle)."""
 import numpy as np
 import pytest
@@ -142,3 +142,21 @@ def test_empty_inputs_are_refused(dm):
         assert fn(one, 1, one, 1, 0, out, None) == -1
     eps = (c_double * 2)()
     assert _native.LIB.dmpt_gershgorin(c_void_p(a.data_ptr()), 0, eps, None) == -1
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("split_fp16", SPLIT_TOL),
+                                           ("fp32", SPLIT_TOL)])
+def test_narrow_gap(dm, precision, tol):
+    """A gap of 0.003 in a spectrum of width 10 (relative to the Gershgorin
+    width: 1.3e-5) at N = 512: about 65 layers, and the forms with 22 or more
+    operand bits stay within their bars (split BF16 does not at this gap:
+    its 16 bits give P1 to about 8e-3)."""
+    from oracle import exact
+    from workloads import dense_gapped_problem
+    p = dense_gapped_problem(512, 256, 0.003, 777, h1="dense", k=1)
+    P0, (P1,), st = _solve(dm, p.H0, p.H1, p.nocc, precision)
+    r0, (r1,) = exact.solve(p.H0, p.H1, p.nocc)
+    e0, e1 = exact.rel_fro(P0, r0), exact.rel_fro(P1, r1)
+    print(f"narrow gap {precision}: layers {st['layers']} err P0 {e0:.1e} P1 {e1:.1e}", flush=True)
+    assert st["converged"] and st["layers"] >= 60
+    assert e0 < tol and e1 < tol

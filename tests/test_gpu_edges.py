@@ -1,7 +1,8 @@
 """Edge cases and full-size parity of the HIP path against the FP64 oracle:
 the smallest problem (N = 2, the 2x2 closed form), extreme occupations, a zero
 perturbation, the maximum number of responses, empty inputs (refused), a
-narrow gap, and configurations 2 and 3 at their full sizes (N = 4096 with three coordinate perturbations; N = 16384
+narrow gap, scale and shift invariances, and configurations 2 and 3 at their
+full sizes (N = 4096 with three coordinate perturbations; N = 16384
 banded against the exact factored oracle)."""
 import numpy as np
 import pytest
@@ -160,3 +161,37 @@ def test_narrow_gap(dm, precision, tol):
     print(f"narrow gap {precision}: layers {st['layers']} err P0 {e0:.1e} P1 {e1:.1e}", flush=True)
     assert st["converged"] and st["layers"] >= 60
     assert e0 < tol and e1 < tol
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "split_bf16"])
+def test_perturbation_scale_is_carried_exactly(dm, precision):
+    """P1 is linear in H1 and the split forms carry S1's magnitude in a
+    power-of-two scale, so H1 scaled by 2^20 or 2^-27 gives P1 scaled by the
+    same power of two, bitwise, with no overflow of the 16-bit splits."""
+    from workloads import config1
+    p = config1(n=300)
+    _, (base,), st = _solve(dm, p.H0, p.H1, p.nocc, precision)
+    for e in (20, -27):
+        f = 2.0 ** e
+        _, (P1,), s = _solve(dm, p.H0, [p.H1[0] * f], p.nocc, precision)
+        assert s["layers"] == st["layers"] and s["d1_layer"] == st["d1_layer"]
+        assert np.array_equal(P1, base * f), e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_fp16"])
+def test_hamiltonian_scale_and_shift(dm, precision):
+    """The normalisation layer (Sec. III.A) maps H0 and H1 scaled together by
+    a power of two to the same S0 and S1 bitwise, so P0 and P1 are bitwise
+    unchanged; a shift H0 + c I moves both Gershgorin bounds by c and leaves
+    P0 and P1 unchanged up to the rounding of the shifted bounds."""
+    from workloads import config1
+    p = config1(n=300)
+    P0, (P1,), st = _solve(dm, p.H0, p.H1, p.nocc, precision)
+    f = 2.0 ** -9
+    Q0, (Q1,), s = _solve(dm, p.H0 * f, [p.H1[0] * f], p.nocc, precision)
+    assert s["layers"] == st["layers"]
+    assert np.array_equal(Q0, P0) and np.array_equal(Q1, P1)
+    tol = 1e-12 if precision == "fp64" else SPLIT_TOL
+    R0, (R1,), _ = _solve(dm, p.H0 + 3.0 * np.eye(p.N), p.H1, p.nocc, precision)
+    assert np.linalg.norm(R0 - P0) < tol * np.linalg.norm(P0)
+    assert np.linalg.norm(R1 - P1) < tol * np.linalg.norm(P1)

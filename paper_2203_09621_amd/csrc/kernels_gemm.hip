@@ -1283,14 +1283,16 @@ void product_items(int T, int mode, TileItem* out) {
 }
 
 static int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
+  // set once, by the first launch of any thread (a function-local static is
+  // initialised exactly once even when threads race to it)
+  static const int cus = [] {
+    int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-  }
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    return n;
+  }();
   return cus;
 }
 

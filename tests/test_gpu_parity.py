@@ -314,3 +314,48 @@ def test_tile_choice_does_not_change_results(dm, n):
     (a0, a1, la, da), (b0, b1, lb, db) = outs
     assert (la, da) == (lb, db)
     assert np.array_equal(a0, b0) and np.array_equal(a1, b1)
+
+
+def test_two_contexts_on_two_threads(dm):
+    """Two contexts, each with its own stream and host thread, solving at the
+    same time (the binding releases the interpreter during library calls):
+    every result is bitwise the one the same problem gives alone, so the
+    contexts share no state."""
+    import threading
+    import torch
+    from workloads import config1, config2
+    probs = [config1(n=300), config2(n=520)]
+    inputs = [(_cuda(p.H0), [_cuda(h) for h in p.H1]) for p in probs]
+    torch.cuda.synchronize()
+
+    def solve_three(i, stream):
+        p, (h0, h1s) = probs[i], inputs[i]
+        ctx = dm.dmpt_init(h0, p.nocc, k_max=len(h1s), precision="split_fp16", stream=stream)
+        try:
+            res = []
+            for _ in range(3):
+                P0, P1s, _ = dm.dmpt_response(ctx, h1s)
+                res.append((P0.cpu().numpy(), [q.cpu().numpy() for q in P1s]))
+            return res
+        finally:
+            dm.dmpt_destroy(ctx)
+
+    alone = [solve_three(i, None) for i in range(2)]
+    out, errors = [None, None], []
+
+    def worker(i):
+        try:
+            out[i] = solve_three(i, torch.cuda.Stream())
+        except Exception as exc:        # reported in the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    for i in range(2):
+        for (a0, a1s), (b0, b1s) in zip(out[i], alone[i]):
+            assert np.array_equal(a0, b0)
+            assert all(np.array_equal(x, y) for x, y in zip(a1s, b1s))

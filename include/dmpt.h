@@ -28,7 +28,8 @@
  *     undefined, except ENOCONV from a capped iteration: the outputs then
  *     hold its last layer (or iterate), as each call states.
  *     dmpt_last_error() gives a human-readable reason.
- *   - One context per stream; contexts are not thread-safe.
+ *   - One context per stream; a context is not thread-safe, but distinct
+ *     contexts may be used from different threads at the same time.
  *   - The library owns its workspace (allocated in dmpt_init, released by
  *     dmpt_destroy); H0 may be freed after dmpt_init returns.
  */

@@ -359,3 +359,25 @@ def test_two_contexts_on_two_threads(dm):
         for (a0, a1s), (b0, b1s) in zip(out[i], alone[i]):
             assert np.array_equal(a0, b0)
             assert all(np.array_equal(x, y) for x, y in zip(a1s, b1s))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_fp16"])
+def test_set_hamiltonian_equals_fresh_context(dm, precision):
+    """dmpt_set_hamiltonian reuses the workspace: after it, a response is
+    bitwise the one of a fresh context for the new H0, and going back to the
+    first H0 gives bitwise the first results again."""
+    from workloads import config1
+    pa, pb = config1(n=300), config1(n=300, seed=91)
+    fresh = [_solve(dm, p, precision) for p in (pa, pb)]
+    ctx = dm.dmpt_init(_cuda(pa.H0), pa.nocc, k_max=1, precision=precision)
+    try:
+        got = []
+        for p in (pa, pb, pa):
+            dm.dmpt_set_hamiltonian(ctx, _cuda(p.H0))
+            P0, P1s, st = dm.dmpt_response(ctx, [_cuda(p.H1[0])])
+            got.append((P0.cpu().numpy(), P1s[0].cpu().numpy(), st["layers"]))
+    finally:
+        dm.dmpt_destroy(ctx)
+    for (P0, P1, layers), (F0, F1s, fst) in zip(got, [fresh[0], fresh[1], fresh[0]]):
+        assert layers == fst["layers"]
+        assert np.array_equal(P0, F0) and np.array_equal(P1, F1s[0])

@@ -242,3 +242,34 @@ def test_batch_split_fp16(dm):
         assert np.array_equal(P0[i], q0.cpu().numpy())
         for a, b in zip(P1[i], q1s):
             assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_batch_reuse_with_new_inputs(dm):
+    """One batch, three responses on different input tensors (new device
+    addresses every call; the graph captured on the first call reads the
+    pointer tables): the second equals a fresh batch on its inputs, and the
+    third (the first inputs again) equals the first, bitwise."""
+    from workloads import config4
+    pa = config4(count=12, nmax=400, seed=11)
+    pb = config4(count=12, nmax=400, seed=11)
+    rng = np.random.default_rng(5)
+    for p in pb:                      # same sizes and occupations, new matrices
+        q, _ = np.linalg.qr(rng.normal(size=(p.N, p.N)))
+        p.H0[...] = (q * np.linalg.eigvalsh(p.H0)[None, :]) @ q.T
+        p.H0[...] = 0.5 * (p.H0 + p.H0.T)
+    (fresh_b,), _ = _run(dm, pb)
+    b = dm.dmpt_batch_init([p.N for p in pa], [p.nocc for p in pa], [p.k for p in pa])
+    try:
+        outs = []
+        for probs in (pa, pb, pa):
+            H0 = [_cuda(p.H0) for p in probs]
+            H1 = [[_cuda(h) for h in p.H1] for p in probs]
+            P0, P1, st, _ = dm.dmpt_batch_response(b, H0, H1)
+            outs.append(([x.cpu().numpy() for x in P0], [[x.cpu().numpy() for x in ps] for ps in P1]))
+    finally:
+        dm.dmpt_batch_destroy(b)
+    for i in range(len(pa)):
+        assert np.array_equal(outs[1][0][i], fresh_b[0][i])
+        assert all(np.array_equal(x, y) for x, y in zip(outs[1][1][i], fresh_b[1][i]))
+        assert np.array_equal(outs[2][0][i], outs[0][0][i])
+        assert all(np.array_equal(x, y) for x, y in zip(outs[2][1][i], outs[0][1][i]))

@@ -128,7 +128,9 @@ dmpt_status dmpt_set_hamiltonian(dmpt_ctx* ctx, const double* H0);
  * array of k device pointers, N x N FP64).  The S0 chain is shared; each
  * response has its own D1 test and is frozen once it passes.  Returns
  * ENOCONV when the layer cap is reached first (outputs then hold the last
- * layer).  `st` may be NULL. */
+ * layer).  Every H1 is read before any output is written, and the context
+ * holds its own copy of H0, so P0 and P1[j] may overwrite the H0 given to
+ * dmpt_init and the H1 matrices.  `st` may be NULL. */
 dmpt_status dmpt_response(dmpt_ctx* ctx, const double* const* H1, int32_t k, double* P0,
                           double* const* P1, dmpt_stats* st);
 

@@ -381,3 +381,28 @@ def test_set_hamiltonian_equals_fresh_context(dm, precision):
     for (P0, P1, layers), (F0, F1s, fst) in zip(got, [fresh[0], fresh[1], fresh[0]]):
         assert layers == fst["layers"]
         assert np.array_equal(P0, F0) and np.array_equal(P1, F1s[0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_fp16"])
+def test_outputs_may_overwrite_the_inputs(dm, c1, precision):
+    """dmpt_response reads every H1 before it writes an output, and the
+    context holds its own copy of H0: P0 written over the H0 tensor and P1
+    over the H1 tensor give bitwise the results of separate outputs."""
+    P0r, (P1r,), _ = _solve(dm, c1, precision)
+    h0, h1 = _cuda(c1.H0), _cuda(c1.H1[0])
+    ctx = dm.dmpt_init(h0, c1.nocc, k_max=1, precision=precision)
+    try:
+        dm.dmpt_response(ctx, [h1], P0=h0, P1s=[h1])
+    finally:
+        dm.dmpt_destroy(ctx)
+    assert np.array_equal(h0.cpu().numpy(), P0r) and np.array_equal(h1.cpu().numpy(), P1r)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+@pytest.mark.parametrize("precision", ["fp64", "split_fp16"])
+def test_nonfinite_hamiltonian(dm, c1, bad, precision):
+    h = c1.H0.copy()
+    h[3, 3] = bad
+    with pytest.raises(dm.DmptError) as ei:
+        dm.solve(_cuda(h), [_cuda(c1.H1[0])], c1.nocc, precision=precision)
+    assert ei.value.status == -5
